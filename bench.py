@@ -1,0 +1,198 @@
+"""Benchmark: throughput of the forced D3Q19 step with spread / interpolated
+point forces on one MI355X, with the dominant kernel's HBM roofline and the
+FP64 CPU oracle timed beside it.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME] [--no-cpu]
+
+Default workload: 128^3 periodic box, FP32 deviation storage, tau = 1/2,
+64 seeded singularities (Stokeslets, stresslets, rotlets; strengths uniform
+in [-1e-5, 1e-5]) expanded to their point forces, static, 5000 steps.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+BYTES_PER_NODE = {"fp64": 304, "fp32": 152, "fp16": 76}   # 2 x 19 populations x storage bytes
+
+WORKLOADS = {
+    # name: (shape, storage, tau, kind, n)
+    "singularities128": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
+    "colloids256_fp32": ((256, 256, 256), "fp32", 0.5, "colloids", 10000),
+    "colloids256_fp16": ((256, 256, 256), "fp16", 0.5, "colloids", 10000),
+    "colloids256_fp64": ((256, 256, 256), "fp64", 0.5, "colloids", 10000),
+    "colloids512_fp32": ((512, 512, 512), "fp32", 0.5, "colloids", 100000),
+    "colloids512_fp16": ((512, 512, 512), "fp16", 0.5, "colloids", 100000),
+}
+DESCR = {
+    "singularities": "%d^3 periodic D3Q19 forced MRT, %s deviation storage, tau=1/2, %d seeded point "
+                     "singularities (Stokeslet/stresslet/rotlet, |s|<=1e-5) as %d point forces",
+    "colloids": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=1/2, %d sedimenting point colloids "
+                "(F=-1e-6 z, a=0.117), spread + interpolate + advect every step, counter-force on",
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_lattice.hip", "lbm_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_0707_1299_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_inputs(kind, shape, n):
+    import numpy as np
+    from paper_0707_1299_amd import lbm, workloads
+    L = shape[0]
+    if kind == "singularities":
+        w = workloads.singularities(L=L, n=n)
+        pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
+        return pos, frc, "static", None
+    pos, frc = workloads.colloids(L, n)
+    return pos, frc, "colloid", dict(inv_a=1 / 0.117, inv_aL=0.77)
+
+
+def build_lattice(shape, storage, tau, kind, pos, frc, model):
+    import torch
+    from paper_0707_1299_amd import lbm
+    lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "colloid"), max_points=len(pos))
+    p = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    f = torch.tensor(frc, dtype=torch.float64, device="cuda")
+    if kind == "colloid":
+        lat.add_point_forces(p, f, None, lbm.LB_COLLOIDS, lbm.PointModel(**model))
+    else:
+        lat.add_point_forces(p, f, None, lbm.LB_FORCES_STATIC)
+    return lat, p
+
+
+def traffic_from_profile(name, storage, N):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(kind, shape, storage, tau, pos, frc, model, budget_s=12.0):
+    """The FP64 oracle, as it is, on a bounded number of steps of the same workload."""
+    import numpy as np
+    import oracle
+    box = oracle.Box(shape, tau, 1.0, zero_net_force=(kind == "colloid"))
+    fs = oracle.ForceSet(np.array(pos), np.array(frc), kind=kind,
+                         inv_a=(model or {}).get("inv_a", 0.0), inv_aL=(model or {}).get("inv_aL", 0.0))
+    box.sets = [fs]
+    t0 = time.perf_counter()
+    box.step(1)
+    t1 = time.perf_counter()
+    per = t1 - t0
+    steps = int(max(1, min(200, budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    box.step(steps)
+    dt = time.perf_counter() - t0
+    N = shape[0] * shape[1] * shape[2]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return box, steps + 1, dict(value=round(N * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+                                sample="steps 2..%d of the same workload (%d steps, %.1f s), FP64, OpenMP"
+                                       % (steps + 1, steps, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="singularities128", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=500)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this build "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0707_1299_amd import lbm  # noqa: F401  (fails loudly if the library is missing)
+
+    shape, storage, tau, kind, n = WORKLOADS[a.workload]
+    N = shape[0] * shape[1] * shape[2]
+    pos, frc, fkind, model = make_inputs(kind, shape, n)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model)
+        lat.step(a.warmup)
+        lat.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(a.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.sync()
+        elapsed = t1 - t0
+        ms_per_step = elapsed / a.steps * 1e3
+        mlups = N * a.steps / elapsed / 1e6
+
+        # dominant kernel: HIP events around every fused-step launch on this stream
+        lat.kernel_timing(True)
+        lat.step(a.timing_steps)
+        ktot_ms, nlaunch = lat.kernel_time()
+        lat.kernel_timing(False)
+        kavg_s = ktot_ms / nlaunch / 1e3
+        alg_bytes = BYTES_PER_NODE[storage] * N
+        achieved = alg_bytes / kavg_s / 1e9
+        traffic = traffic_from_profile(a.workload, storage, N)
+
+    out = {
+        "metric": "MLUPS and % HBM roofline; colloid updates/s vs plain FP32 at stated error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32"}[storage],
+        "data": "synthetic",
+        "config": {"workload": DESCR[kind] % ((shape[0], storage, n) + ((len(pos),) if kind == "singularities" else ())),
+                   "nodes": N, "points": int(len(pos)), "seed": 20261200 + (2 if kind == "singularities" else 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_lattice step (fused spread/pull/collide/store/interpolate)",
+                     "bytes_per_node": BYTES_PER_NODE[storage], "kernel_ms": round(kavg_s * 1e3, 5),
+                     "launches_timed": nlaunch},
+    }
+    if kind == "colloid":
+        out["colloid_updates_per_s"] = round(n * a.steps / elapsed, 1)
+
+    if not a.no_cpu:
+        box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
+        out["cpu_baseline"] = cb
+        # same number of steps on a fresh GPU lattice: error of this storage against the oracle
+        with torch.cuda.stream(stream):
+            pos2, frc2, _, _ = make_inputs(kind, shape, n)
+            lat2, _ = build_lattice(shape, storage, tau, fkind, pos2, frc2, model)
+            lat2.step(csteps)
+            _, u = lat2.moments(rho=False)
+            lat2.sync()
+        _, uo = box.moments()
+        err = float(np.abs(u.cpu().numpy()[0] - uo).max() / np.abs(uo).max())
+        out["error_vs_oracle"] = {"velocity_rel_linf": err, "steps": csteps}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,238 @@
+/*
+ * liblbm — forced D3Q19 lattice Boltzmann with off-lattice point forces on
+ * MI355X (gfx950).  C ABI.
+ *
+ * Method: Nash, Adhikari & Cates, "Singular forces and point-like colloids in
+ * lattice Boltzmann hydrodynamics".
+ *   - Fluid step: the second-order forced LBE in auxiliary populations fbar
+ *     (Sec. II, Eq. transformf and Eq. halftransform) with the projected-ghost
+ *     MRT collision of Eq. fiexp: ghosts set to zero, all six stress modes
+ *     relaxed at 1/tau, momentum A = sum fbar c + rho F, and stress
+ *     B = S - omega (S - rho v v - tau (v F + F v)), omega = 1/(tau + 1/2)
+ *     (the sign of the (S - rho v v) term is the one the general scheme
+ *     Eq. mrtlbe implies).
+ *   - Point forces: spread with Peskin's 4-point regularised delta,
+ *     Eq. deltadef, F(r) = sum_a f_a deltaP(r - R_a) (Sec. III).
+ *   - Fluid velocity at the particles: interpolated with the same kernel
+ *     (Sec. IV), and colloids advanced by
+ *     dR/dt = v(R) + F/(6 pi eta) (1/a - 1/a_L)   (Sec. IV).
+ *
+ * Conventions.  Lattice units dx = dt = 1.  Periodic boxes of nx*ny*nz nodes
+ * at integer coordinates.  tau is the paper's relaxation time: the shear
+ * viscosity is eta = rho0 tau / 3.  The grid field is the force density
+ * g = rho F.  The physical velocity is u = (sum fbar c + g/2) / rho.
+ * Populations are stored as deviations fbar_i - w_i rho0.
+ *
+ * Memory.  The caller owns all device memory: it allocates the workspace
+ * (lb_workspace_bytes) and every input/output array, and must keep them alive
+ * while work that uses them may still run.  The library allocates no device
+ * memory.  Every call enqueues asynchronously on the stream given to lb_init
+ * (or lb_set_stream) and returns without waiting, except lb_sync,
+ * lb_diagnostics and lb_kernel_time, which wait for the stream.
+ *
+ * Errors.  Every int-returning call returns LB_OK (0) or a negative status;
+ * lb_status_string() names it and lb_last_error() gives the context's last
+ * message.  No exception crosses the ABI.  A device fault surfaces as
+ * LB_ERR_HIP at the next call that checks the stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LB_OK 0
+#define LB_ERR_ARG (-1)       /* invalid argument */
+#define LB_ERR_SIZE (-2)      /* workspace too small / size limits */
+#define LB_ERR_HIP (-3)       /* HIP runtime error */
+#define LB_ERR_NONFINITE (-4) /* non-finite value or FP16 overflow detected */
+#define LB_ERR_CAPACITY (-5)  /* more point forces than max_points */
+#define LB_ERR_STATE (-6)     /* call not valid in the current state */
+
+/* population storage */
+#define LB_STORAGE_FP64 0 /* FP64 deviations, FP64 arithmetic */
+#define LB_STORAGE_FP32 1 /* FP32 deviations, FP32 arithmetic */
+#define LB_STORAGE_FP16 2 /* FP16 (fbar_i - w_i rho0)/w_i * 2^e per box, FP32 arithmetic */
+
+/* point-force set kinds */
+#define LB_FORCES_NEXT_STEP 0 /* applied in the next step only, then dropped */
+#define LB_FORCES_STATIC 1    /* applied every step at fixed positions */
+#define LB_COLLOIDS 2         /* applied every step; positions advanced in place */
+
+#define LB_MAX_SETS 16
+#define LB_NDIAG 12 /* values per box returned by lb_diagnostics */
+
+/* MLP of the learned mobility correction: 4 -> 64 tanh -> 64 tanh -> 1 */
+#define LBML_NPARAM 4545
+
+typedef struct lb_params {
+    int32_t nx, ny, nz;     /* nodes per box along x, y, z; each >= 4 */
+    int32_t nboxes;         /* independent periodic boxes of that size, >= 1 */
+    int32_t storage;        /* LB_STORAGE_* */
+    int32_t zero_net_force; /* 1: add the uniform density -sum F / N per box */
+    double rho0;            /* reference density (> 0); 0 means 1 */
+    const double* tau;      /* HOST array [nboxes]: paper's tau (> 0) per box */
+    int64_t max_points;     /* capacity: point forces over all sets at once */
+    int32_t tile_x;         /* tile shape (nodes); 0 = default. tile_x*tile_y*tile_z = 256 */
+    int32_t tile_y;
+    int32_t tile_z;
+    int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default */
+} lb_params;
+
+/*
+ * Per-set options for lb_add_point_forces.  For LB_COLLOIDS, inv_a = 1/a and
+ * inv_aL = 1/a_L enter the update of Sec. IV; 1/a - 1/a_L must be > 0 (the
+ * renormalised radius a_R is positive only for a < a_L).  If d_mlp is not
+ * NULL, 1/a_L at each particle is inv_aL + out_scale * MLP(x) with
+ * x_k = (raw_k - in_shift[k]) * in_scale[k] and raw = (frac(Rx), frac(Ry),
+ * frac(Rz), tau of the particle's box); d_mlp holds LBML_NPARAM bfloat16
+ * weights in the lbml layout.  d_vel_out (n,3) FP64 receives the interpolated
+ * fluid velocity v(R) of the last step; d_vel_sum (n,3) FP64 is incremented by
+ * it every step (the caller zeroes it).  Either may be NULL.
+ */
+typedef struct lb_point_model {
+    double inv_a;
+    double inv_aL;
+    const uint16_t* d_mlp;
+    float in_shift[4];
+    float in_scale[4];
+    float out_scale;
+    double* d_vel_out;
+    double* d_vel_sum;
+} lb_point_model;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Device bytes the workspace must have for these parameters.  Pure function. */
+int lb_workspace_bytes(const lb_params* p, size_t* bytes);
+
+/*
+ * Create a context on the caller's workspace (device pointer, >= the queried
+ * size, 256-byte aligned) and set every box to rest (fbar = w rho0, i.e. zero
+ * deviation).  hip_stream is a hipStream_t (NULL = the null stream).  The
+ * context holds, but does not own, the workspace.
+ */
+int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_stream, lb_ctx** out);
+
+/* Redirect subsequent work to another stream. */
+int lb_set_stream(lb_ctx* ctx, void* hip_stream);
+
+/*
+ * Set the auxiliary populations of every node to the equilibrium of Eq. eqf at
+ * the given density and velocity: d_rho (nboxes,nz,ny,nx) and d_u
+ * (nboxes,3,nz,ny,nx), FP64 device arrays.
+ */
+int lb_set_equilibrium(lb_ctx* ctx, const double* d_rho, const double* d_u);
+
+/*
+ * Register n point forces: d_pos and d_force are (n,3) FP64 device arrays,
+ * positions in lattice units (wrapped periodically), forces in lattice units
+ * (force per step).  d_box (n) int32 names each point's box, or NULL for box 0.
+ * kind is one of the LB_FORCES_ kinds or LB_COLLOIDS; model may be NULL except for colloids.
+ * The arrays are read at every step that applies them and must stay valid
+ * until then (stream order).  Forces spread per Sec. III; multipoles are
+ * passed as their point forces (see lb_expand_multipoles).
+ */
+int lb_add_point_forces(lb_ctx* ctx, int64_t n, const double* d_pos, const double* d_force,
+                        const int32_t* d_box, int kind, const lb_point_model* model);
+
+/* Drop every registered set. */
+int lb_clear_forces(lb_ctx* ctx);
+
+/*
+ * Advance nsteps steps.  Each step: spread the registered forces at the
+ * current positions, collide every node with them (Eq. fiexp), interpolate the
+ * physical velocity u at the points with the same kernel, propagate (the split
+ * after Eq. halftransform), then advance colloids by the Sec. IV update
+ * (explicit Euler).  Repeated chunks run as a captured HIP graph.
+ */
+int lb_step(lb_ctx* ctx, int32_t nsteps);
+
+/*
+ * Physical moments at the current time with the registered forces
+ * (Eq. macrovariables2): d_rho (nboxes,nz,ny,nx), d_u (nboxes,3,nz,ny,nx),
+ * FP64 device arrays; d_rho may be NULL.
+ */
+int lb_moments(lb_ctx* ctx, double* d_rho, double* d_u);
+
+/*
+ * Interpolated physical velocity U(R) = sum_x u(x) deltaP(x - R) (Sec. IV) at
+ * n arbitrary points: d_pos (n,3) FP64, d_box (n) int32 or NULL, d_u_out (n,3).
+ */
+int lb_interp_velocity(lb_ctx* ctx, int64_t n, const double* d_pos, const int32_t* d_box, double* d_u_out);
+
+/*
+ * FP64 diagnostics per box, written to HOST h_out[nboxes][LB_NDIAG]:
+ *   0 sum drho, 1-3 sum jbar (auxiliary momentum), 4-6 sum g,
+ *   7-9 sum x cross g (node coordinates in the box), 10 max |u|,
+ *   11 count of non-finite nodes.  Waits for the stream.  Returns
+ *   LB_ERR_NONFINITE if any box holds a non-finite value.
+ */
+int lb_diagnostics(lb_ctx* ctx, double* h_out);
+
+/* Wait for the stream; reports a pending device error or non-finite flag. */
+int lb_sync(lb_ctx* ctx);
+
+/* Release the context (host memory and cached graphs); the workspace stays the caller's. */
+int lb_destroy(lb_ctx* ctx);
+
+const char* lb_status_string(int status);
+const char* lb_last_error(const lb_ctx* ctx);
+
+/* Steps taken since lb_init. */
+int64_t lb_steps_taken(const lb_ctx* ctx);
+
+/*
+ * Timing of the fused step kernel: with enable = 1, lb_step launches eagerly
+ * and brackets every fused-kernel launch with HIP events on the context's
+ * stream; lb_kernel_time waits for the stream and returns the summed
+ * duration (ms) and the number of launches since it was enabled.
+ */
+int lb_kernel_timing(lb_ctx* ctx, int enable);
+int lb_kernel_time(lb_ctx* ctx, double* total_ms, int64_t* launches);
+
+/*
+ * Multipoles of Sec. III as point forces (HOST arrays, host computation).
+ * type[i]: 0 Stokeslet (s p at R), 1 stresslet (+s p at R + d/2 p and
+ * -s p at R - d/2 p), 2 rotlet (with e2 = n x e1: +s e2 at R + d/2 e1,
+ * -s e2 at R - d/2 e1, -s e1 at R + d/2 e2, +s e1 at R - d/2 e2: zero net
+ * force, zero symmetric part, torque 2 d s n).  axis is p (types 0, 1) or
+ * n (type 2), unit; e1 is a unit vector normal to n.  Outputs hold up to
+ * 4 n points; *n_out receives the count.  Points keep the input order.
+ */
+int lb_expand_multipoles(int64_t n, const int32_t* type, const double* center, const double* axis,
+                         const double* e1, const double* strength, double sep, int64_t* n_out,
+                         double* pos_out, double* force_out);
+
+/*
+ * Mobility-correction MLP (not in the paper: it predicts the
+ * lattice-position dependence of 1/a_L defined in Sec. IV / Appendix A).
+ * Parameter layout (flat): W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1].
+ * Device arrays; stream-ordered on hip_stream.
+ *   lbml_round_bf16: w16[i] = bf16(master[i]) (round to nearest even).
+ *   lbml_forward:    y[n] = MLP(x[n][4]) with bf16 weights, FP32 accumulation.
+ *   lbml_loss_grad:  grad[LBML_NPARAM] (FP32) = d/dtheta mean((y - target)^2)
+ *                    at the bf16 weights, and *loss (FP32 device scalar);
+ *                    deterministic (fixed reduction order).  work must hold
+ *                    lbml_work_floats(n) floats.
+ *   lbml_adam_step:  one Adam update (Kingma & Ba) of master/m/v at iteration t
+ *                    and re-rounding of w16.
+ */
+int64_t lbml_work_floats(int64_t n);
+int lbml_round_bf16(const float* d_master, uint16_t* d_w16, void* hip_stream);
+int lbml_forward(const uint16_t* d_w16, int64_t n, const float* d_x, float* d_y, void* hip_stream);
+int lbml_loss_grad(const uint16_t* d_w16, int64_t n, const float* d_x, const float* d_target, float* d_grad,
+                   float* d_loss, float* d_work, void* hip_stream);
+int lbml_adam_step(float* d_master, float* d_m, float* d_v, const float* d_grad, uint16_t* d_w16, int32_t t,
+                   float lr, float beta1, float beta2, float eps, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

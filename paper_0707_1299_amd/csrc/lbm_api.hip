@@ -1,0 +1,696 @@
+// liblbm host runtime: the C ABI declared in include/lbm.h.
+//
+// The context owns no device memory: it carves the caller's workspace into
+// the two population copies (pull scheme, A/B), per-box parameters, the
+// per-point records, the tile bins and the scratch of the reductions, and
+// enqueues every kernel on the caller's stream.  Repeated steps are captured
+// once per (parity, force-set generation) into a HIP graph of two steps and
+// replayed.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t storage_bytes(int st) { return st == LB_STORAGE_FP64 ? 8 : (st == LB_STORAGE_FP32 ? 4 : 2); }
+
+size_t rec_bytes(int st) { return st == LB_STORAGE_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>); }
+
+int max_axis_tiles(int n, int t)
+{
+    int best = 0;
+    for (int b = 0; b < n; ++b) {
+        int seen[4], cnt = 0;
+        for (int k = 0; k < 4; ++k) {
+            const int tile = ((b + k) % n) / t;
+            bool dup = false;
+            for (int j = 0; j < cnt; ++j) dup |= seen[j] == tile;
+            if (!dup) seen[cnt++] = tile;
+        }
+        best = std::max(best, cnt);
+    }
+    return best;
+}
+
+struct Layout {
+    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, pslot, partial, fpart, ticket, err, diag, diagout;
+    size_t total;
+};
+
+struct Plan {
+    Geom G;
+    Layout L;
+    int chunks;
+    long long cap;
+};
+
+void choose_tile(const lb_params* p, int& tx, int& ty, int& tz)
+{
+    if (p->tile_x > 0) {
+        tx = p->tile_x;
+        ty = p->tile_y;
+        tz = p->tile_z;
+        return;
+    }
+    if (p->nx >= 64) {
+        tx = 64; ty = 2; tz = 2;
+    } else if (p->nx >= 32) {
+        tx = 32; ty = 4; tz = 2;
+    } else {
+        tx = 16; ty = 4; tz = 4;
+    }
+}
+
+int make_plan(const lb_params* p, Plan& P, std::string& why)
+{
+    if (!p) { why = "params is NULL"; return LB_ERR_ARG; }
+    if (p->nx < 4 || p->ny < 4 || p->nz < 4) { why = "each of nx, ny, nz must be >= 4"; return LB_ERR_ARG; }
+    if (p->nboxes < 1) { why = "nboxes must be >= 1"; return LB_ERR_ARG; }
+    if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_FP16) { why = "unknown storage"; return LB_ERR_ARG; }
+    if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
+    if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
+    int tx, ty, tz;
+    choose_tile(p, tx, ty, tz);
+    if (!tile_supported(tx, ty, tz)) { why = "unsupported tile shape"; return LB_ERR_ARG; }
+    Geom& G = P.G;
+    memset(&G, 0, sizeof(G));
+    G.nx = p->nx; G.ny = p->ny; G.nz = p->nz; G.nboxes = p->nboxes;
+    G.tx = tx; G.ty = ty; G.tz = tz;
+    G.ntx = (p->nx + tx - 1) / tx;
+    G.nty = (p->ny + ty - 1) / ty;
+    G.ntz = (p->nz + tz - 1) / tz;
+    G.N = (long long)p->nx * p->ny * p->nz;
+    G.sp = (G.N + 255) / 256 * 256 + 64;
+    G.sbox = (long long)NQ * G.sp;
+    G.tiles_per_box = (long long)G.ntx * G.nty * G.ntz;
+    G.ntiles = G.tiles_per_box * p->nboxes;
+    G.rho0 = p->rho0 > 0.0 ? p->rho0 : 1.0;
+    G.maxp = max_axis_tiles(p->nx, tx) * max_axis_tiles(p->ny, ty) * max_axis_tiles(p->nz, tz);
+    if (G.ntiles >= (1LL << 31) - 1) { why = "too many tiles"; return LB_ERR_SIZE; }
+    P.cap = p->max_points;
+    if (P.cap * G.maxp >= (1LL << 31) - 1) { why = "max_points too large"; return LB_ERR_SIZE; }
+    P.chunks = box_chunks();
+    Layout& L = P.L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+    const size_t popb = (size_t)G.sbox * p->nboxes * storage_bytes(p->storage);
+    L.pop[0] = take(popb);
+    L.pop[1] = take(popb);
+    L.boxes = take(sizeof(BoxDev) * p->nboxes);
+    L.rec = take(rec_bytes(p->storage) * P.cap);
+    L.count = take(sizeof(int) * G.ntiles);
+    L.cursor = take(sizeof(int) * G.ntiles);
+    L.toff = take(sizeof(int) * (G.ntiles + 1));
+    L.bsum = take(sizeof(int) * scan_blocks(G.ntiles));
+    L.tlist = take(sizeof(int) * P.cap * G.maxp);
+    L.pslot = take(sizeof(int) * P.cap * G.maxp);
+    L.partial = take(sizeof(double) * 3 * P.cap * G.maxp);
+    L.fpart = take(sizeof(double) * 3 * p->nboxes * P.chunks);
+    L.ticket = take(sizeof(unsigned) * p->nboxes);
+    L.err = take(sizeof(int) * 4);
+    L.diag = take(sizeof(double) * LBD_N * G.ntiles);
+    L.diagout = take(sizeof(double) * LBD_N * p->nboxes);
+    L.total = o;
+    return LB_OK;
+}
+
+struct Set {
+    long long n;
+    const double* pos;
+    const double* frc;
+    const int* box;
+    int kind;
+    lb_point_model model;
+    bool has_model;
+};
+
+struct GraphEntry {
+    int parity;
+    unsigned long long gen;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    std::vector<double> tau;
+    Plan P;
+    char* ws;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    int cur;
+    std::vector<Set> sets;
+    unsigned long long gen;
+    bool bins_valid;
+    std::vector<GraphEntry> graphs;
+    bool timing;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used;
+    double timed_ms;
+    long long timed_launches;
+    long long steps;
+    std::vector<BoxDev> hboxes;
+    std::string err;
+
+    void* pop(int k) const { return ws + P.L.pop[k]; }
+    BoxDev* boxes() const { return (BoxDev*)(ws + P.L.boxes); }
+    void* rec() const { return ws + P.L.rec; }
+    int* count() const { return (int*)(ws + P.L.count); }
+    int* cursor() const { return (int*)(ws + P.L.cursor); }
+    int* toff() const { return (int*)(ws + P.L.toff); }
+    int* bsum() const { return (int*)(ws + P.L.bsum); }
+    int* tlist() const { return (int*)(ws + P.L.tlist); }
+    int* pslot() const { return (int*)(ws + P.L.pslot); }
+    double* partial() const { return (double*)(ws + P.L.partial); }
+    double* fpart() const { return (double*)(ws + P.L.fpart); }
+    unsigned* ticket() const { return (unsigned*)(ws + P.L.ticket); }
+    int* errw() const { return (int*)(ws + P.L.err); }
+    double* diag() const { return (double*)(ws + P.L.diag); }
+    double* diagout() const { return (double*)(ws + P.L.diagout); }
+};
+
+namespace {
+
+int fail(lb_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_check(lb_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LB_OK;
+    return fail(c, LB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+long long total_points(const lb_ctx* c)
+{
+    long long n = 0;
+    for (auto& s : c->sets) n += s.n;
+    return n;
+}
+
+bool has_kind(const lb_ctx* c, int kind)
+{
+    for (auto& s : c->sets)
+        if (s.kind == kind) return true;
+    return false;
+}
+
+// records + tile bins for the current point positions
+void build_points(lb_ctx* c, hipStream_t s)
+{
+    const Geom& G = c->P.G;
+    long long off = 0;
+    for (auto& st : c->sets) {
+        launch_prep(c->p.storage, G, st.n, off, st.pos, st.frc, st.box, c->rec(), c->count(), c->pslot(), c->errw(),
+                    s);
+        off += st.n;
+    }
+    launch_bins(c->p.storage, G, off, c->rec(), c->count(), c->bsum(), c->toff(), c->cursor(), c->tlist(),
+                c->pslot(), s);
+}
+
+void box_update(lb_ctx* c, hipStream_t s, bool fp16_exp)
+{
+    const bool zero_net = c->p.zero_net_force != 0;
+    const bool fp16 = fp16_exp && c->p.storage == LB_STORAGE_FP16;
+    if (!zero_net && !fp16) return;
+    launch_box_update(c->p.storage, c->P.G, c->rec(), total_points(c) > 0 ? c->toff() : nullptr, c->tlist(),
+                      c->fpart(), c->ticket(), c->boxes(), zero_net ? 1 : 0, fp16 ? 1 : 0, s);
+}
+
+// one step on stream s; flips c->cur
+void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
+{
+    const Geom& G = c->P.G;
+    const long long npts = total_points(c);
+    if (npts > 0 && rebuild) build_points(c, s);
+    box_update(c, s, true);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->ev_used + 2 > c->ev.size()) {
+            for (int k = 0; k < 256; ++k) {
+                hipEvent_t e;
+                (void)hipEventCreate(&e);
+                c->ev.push_back(e);
+            }
+        }
+        e0 = c->ev[c->ev_used++];
+        e1 = c->ev[c->ev_used++];
+        (void)hipEventRecord(e0, s);
+    }
+    launch_lattice(c->p.storage, G, 0, c->pop(c->cur), c->pop(c->cur ^ 1), c->boxes(), npts > 0 ? c->toff() : nullptr,
+                   c->tlist(), c->rec(), c->partial(), nullptr, s);
+    if (c->timing) {
+        (void)hipEventRecord(e1, s);
+        c->timed_launches++;
+    }
+    long long off = 0;
+    for (auto& st : c->sets) {
+        const bool adv = st.kind == LB_COLLOIDS;
+        const bool outs = st.has_model && (st.model.d_vel_out || st.model.d_vel_sum);
+        if (adv || outs) {
+            AdvectLaunch a;
+            memset(&a, 0, sizeof(a));
+            a.n = st.n;
+            a.off = off;
+            a.frc = st.frc;
+            a.pos = (double*)st.pos;
+            a.boxid = st.box;
+            a.advect = adv ? 1 : 0;
+            if (st.has_model) {
+                a.vel_out = st.model.d_vel_out;
+                a.vel_sum = st.model.d_vel_sum;
+                a.inv_a = st.model.inv_a;
+                a.inv_aL = st.model.inv_aL;
+                a.mlp = st.model.d_mlp;
+                for (int k = 0; k < 4; ++k) {
+                    a.in_shift[k] = st.model.in_shift[k];
+                    a.in_scale[k] = st.model.in_scale[k];
+                }
+                a.out_scale = st.model.out_scale;
+            }
+            launch_advect(G, a, c->boxes(), c->pslot(), c->partial(), s);
+        }
+        off += st.n;
+    }
+    c->cur ^= 1;
+}
+
+void drop_graphs(lb_ctx* c)
+{
+    for (auto& g : c->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+int get_graph(lb_ctx* c, bool rebuild, hipGraphExec_t* out)
+{
+    for (auto& g : c->graphs)
+        if (g.parity == c->cur && g.gen == c->gen) {
+            *out = g.exec;
+            return LB_OK;
+        }
+    if (!c->cap_stream) {
+        int r = hip_check(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+        if (r) return r;
+    }
+    const int parity = c->cur;
+    int r = hip_check(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    if (r) return r;
+    enqueue_step(c, c->cap_stream, rebuild);
+    enqueue_step(c, c->cap_stream, rebuild);
+    hipGraph_t graph;
+    r = hip_check(c, hipStreamEndCapture(c->cap_stream, &graph), "hipStreamEndCapture");
+    if (r) return r;
+    hipGraphExec_t exec;
+    r = hip_check(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (r) {
+        (void)hipGraphDestroy(graph);
+        return r;
+    }
+    c->graphs.push_back({parity, c->gen, graph, exec});
+    *out = exec;
+    return LB_OK;
+}
+
+int check_async(lb_ctx* c)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, LB_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_workspace_bytes(const lb_params* p, size_t* bytes)
+{
+    if (!bytes) return LB_ERR_ARG;
+    Plan P;
+    std::string why;
+    const int r = make_plan(p, P, why);
+    if (r) return r;
+    *bytes = P.L.total;
+    return LB_OK;
+}
+
+int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_stream, lb_ctx** out)
+{
+    if (!out) return LB_ERR_ARG;
+    *out = nullptr;
+    Plan P;
+    std::string why;
+    int r = make_plan(p, P, why);
+    if (r) return r;
+    if (!p->tau) return LB_ERR_ARG;
+    for (int b = 0; b < p->nboxes; ++b)
+        if (!(p->tau[b] > 0.0) || !isfinite(p->tau[b])) return LB_ERR_ARG;
+    if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return LB_ERR_ARG;
+    if (bytes < P.L.total) return LB_ERR_SIZE;
+    lb_ctx* c = new lb_ctx();
+    c->p = *p;
+    c->tau.assign(p->tau, p->tau + p->nboxes);
+    c->p.tau = c->tau.data();
+    c->P = P;
+    c->ws = (char*)d_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->cap_stream = nullptr;
+    c->cur = 0;
+    c->gen = 1;
+    c->bins_valid = false;
+    c->timing = false;
+    c->ev_used = 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    c->steps = 0;
+    const int e0 = p->fp16_exponent != 0 ? p->fp16_exponent : 30;
+    c->hboxes.resize(p->nboxes);
+    for (int b = 0; b < p->nboxes; ++b) {
+        BoxDev& B = c->hboxes[b];
+        memset(&B, 0, sizeof(B));
+        B.tau = p->tau[b];
+        B.omega = 1.0 / (p->tau[b] + 0.5);
+        B.e_data = e0;
+        B.s_in = ldexpf(1.0f, -e0);
+        B.s_out = ldexpf(1.0f, e0);
+    }
+    hipStream_t s = c->stream;
+    const Geom& G = c->P.G;
+    const size_t popb = (size_t)G.sbox * p->nboxes * storage_bytes(p->storage);
+    launch_fill_u32(c->pop(0), (long long)(popb / 4), 0u, s);
+    launch_fill_u32(c->pop(1), (long long)(popb / 4), 0u, s);
+    launch_fill_u32(c->count(), G.ntiles, 0u, s);
+    launch_fill_u32(c->cursor(), G.ntiles, 0u, s);
+    launch_fill_u32(c->toff(), G.ntiles + 1, 0u, s);
+    launch_fill_u32(c->ticket(), p->nboxes, 0u, s);
+    launch_fill_u32(c->errw(), 4, 0u, s);
+    r = hip_check(c, hipMemcpyAsync(c->boxes(), c->hboxes.data(), sizeof(BoxDev) * p->nboxes, hipMemcpyHostToDevice, s),
+                  "hipMemcpyAsync");
+    if (!r) r = check_async(c);
+    if (r) {
+        delete c;
+        return r;
+    }
+    *out = c;
+    return LB_OK;
+}
+
+int lb_set_stream(lb_ctx* c, void* hip_stream)
+{
+    if (!c) return LB_ERR_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return LB_OK;
+}
+
+int lb_set_equilibrium(lb_ctx* c, const double* d_rho, const double* d_u)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!d_rho || !d_u) return fail(c, LB_ERR_ARG, "lb_set_equilibrium: NULL field");
+    launch_equilibrium(c->p.storage, c->P.G, c->pop(c->cur), c->boxes(), d_rho, d_u, c->stream);
+    return check_async(c);
+}
+
+int lb_add_point_forces(lb_ctx* c, int64_t n, const double* d_pos, const double* d_force, const int32_t* d_box,
+                        int kind, const lb_point_model* model)
+{
+    if (!c) return LB_ERR_ARG;
+    if (n < 0) return fail(c, LB_ERR_ARG, "n < 0");
+    if (n > 0 && (!d_pos || !d_force)) return fail(c, LB_ERR_ARG, "NULL positions or forces");
+    if (kind != LB_FORCES_NEXT_STEP && kind != LB_FORCES_STATIC && kind != LB_COLLOIDS)
+        return fail(c, LB_ERR_ARG, "unknown kind");
+    if (kind == LB_COLLOIDS) {
+        if (!model) return fail(c, LB_ERR_ARG, "colloids need a model (a, a_L)");
+        if (!(model->inv_a > model->inv_aL) || !isfinite(model->inv_a) || !isfinite(model->inv_aL))
+            return fail(c, LB_ERR_ARG, "need 1/a > 1/a_L (a < a_L) for a positive renormalised radius");
+    }
+    if ((int)c->sets.size() >= LB_MAX_SETS) return fail(c, LB_ERR_CAPACITY, "too many sets");
+    if (total_points(c) + n > c->P.cap) return fail(c, LB_ERR_CAPACITY, "more points than max_points");
+    if (n == 0) return LB_OK;
+    Set s;
+    s.n = n;
+    s.pos = d_pos;
+    s.frc = d_force;
+    s.box = (const int*)d_box;
+    s.kind = kind;
+    s.has_model = model != nullptr;
+    if (model)
+        s.model = *model;
+    else
+        memset(&s.model, 0, sizeof(s.model));
+    c->sets.push_back(s);
+    c->gen++;
+    c->bins_valid = false;
+    return LB_OK;
+}
+
+int lb_clear_forces(lb_ctx* c)
+{
+    if (!c) return LB_ERR_ARG;
+    c->sets.clear();
+    c->gen++;
+    c->bins_valid = false;
+    return LB_OK;
+}
+
+int lb_step(lb_ctx* c, int32_t nsteps)
+{
+    if (!c) return LB_ERR_ARG;
+    if (nsteps < 0) return fail(c, LB_ERR_ARG, "nsteps < 0");
+    if (nsteps == 0) return LB_OK;
+    int left = nsteps;
+    if (has_kind(c, LB_FORCES_NEXT_STEP)) {
+        enqueue_step(c, c->stream, true);
+        c->sets.erase(std::remove_if(c->sets.begin(), c->sets.end(),
+                                     [](const Set& s) { return s.kind == LB_FORCES_NEXT_STEP; }),
+                      c->sets.end());
+        c->gen++;
+        c->bins_valid = false;
+        c->steps++;
+        left--;
+    }
+    const bool moving = has_kind(c, LB_COLLOIDS);
+    const bool pts = total_points(c) > 0;
+    if (left > 0 && pts && !moving && !c->bins_valid) {
+        build_points(c, c->stream);
+        c->bins_valid = true;
+    }
+    const bool rebuild = moving;
+    if (c->timing || left < 4) {
+        for (int k = 0; k < left; ++k) enqueue_step(c, c->stream, rebuild);
+    } else {
+        hipGraphExec_t exec;
+        int r = get_graph(c, rebuild, &exec);
+        if (r) return r;
+        for (int k = 0; k + 1 < left; k += 2) {
+            r = hip_check(c, hipGraphLaunch(exec, c->stream), "hipGraphLaunch");
+            if (r) return r;
+        }
+        if (left & 1) enqueue_step(c, c->stream, rebuild);
+    }
+    c->steps += left;
+    return check_async(c);
+}
+
+static int prepare_fields(lb_ctx* c)
+{
+    if (total_points(c) > 0) {
+        build_points(c, c->stream);
+        if (!has_kind(c, LB_COLLOIDS)) c->bins_valid = true;
+    }
+    box_update(c, c->stream, false);
+    return LB_OK;
+}
+
+int lb_moments(lb_ctx* c, double* d_rho, double* d_u)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!d_u) return fail(c, LB_ERR_ARG, "lb_moments: d_u is NULL");
+    prepare_fields(c);
+    launch_lattice(c->p.storage, c->P.G, 1, c->pop(c->cur), nullptr, c->boxes(),
+                   total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), d_rho, d_u, c->stream);
+    return check_async(c);
+}
+
+int lb_interp_velocity(lb_ctx* c, int64_t n, const double* d_pos, const int32_t* d_box, double* d_u_out)
+{
+    if (!c) return LB_ERR_ARG;
+    if (n < 0) return fail(c, LB_ERR_ARG, "n < 0");
+    if (n == 0) return LB_OK;
+    if (!d_pos || !d_u_out) return fail(c, LB_ERR_ARG, "NULL positions or output");
+    prepare_fields(c);
+    launch_interp_points(c->p.storage, c->P.G, n, d_pos, (const int*)d_box, d_u_out, c->pop(c->cur), c->boxes(),
+                         total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), c->stream);
+    return check_async(c);
+}
+
+static int read_flags(lb_ctx* c)
+{
+    int errw[4];
+    int r = hip_check(c, hipMemcpyAsync(errw, c->errw(), sizeof(errw), hipMemcpyDeviceToHost, c->stream), "hipMemcpy");
+    if (r) return r;
+    std::vector<BoxDev> hb(c->p.nboxes);
+    r = hip_check(c, hipMemcpyAsync(hb.data(), c->boxes(), sizeof(BoxDev) * c->p.nboxes, hipMemcpyDeviceToHost,
+                                    c->stream),
+                  "hipMemcpy");
+    if (r) return r;
+    r = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (r) return r;
+    if (errw[0] & 1) {
+        launch_fill_u32(c->errw(), 4, 0u, c->stream);
+        return fail(c, LB_ERR_ARG, "a point names a box id out of range");
+    }
+    if (errw[0] & 2) {
+        launch_fill_u32(c->errw(), 4, 0u, c->stream);
+        return fail(c, LB_ERR_NONFINITE, "non-finite point position or force");
+    }
+    for (int b = 0; b < c->p.nboxes; ++b)
+        if (hb[b].nonfinite) return fail(c, LB_ERR_NONFINITE, "non-finite value or FP16 overflow in box " + std::to_string(b));
+    return LB_OK;
+}
+
+int lb_diagnostics(lb_ctx* c, double* h_out)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!h_out) return fail(c, LB_ERR_ARG, "h_out is NULL");
+    prepare_fields(c);
+    const Geom& G = c->P.G;
+    launch_lattice(c->p.storage, G, 2, c->pop(c->cur), nullptr, c->boxes(), total_points(c) > 0 ? c->toff() : nullptr,
+                   c->tlist(), c->rec(), c->diag(), nullptr, c->stream);
+    launch_diag_reduce(G, c->diag(), c->diagout(), c->stream);
+    int r = check_async(c);
+    if (r) return r;
+    r = hip_check(c,
+                  hipMemcpyAsync(h_out, c->diagout(), sizeof(double) * LBD_N * c->p.nboxes, hipMemcpyDeviceToHost,
+                                 c->stream),
+                  "hipMemcpy");
+    if (r) return r;
+    return read_flags(c);
+}
+
+int lb_sync(lb_ctx* c)
+{
+    if (!c) return LB_ERR_ARG;
+    int r = check_async(c);
+    if (r) return r;
+    return read_flags(c);
+}
+
+int lb_destroy(lb_ctx* c)
+{
+    if (!c) return LB_ERR_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return LB_OK;
+}
+
+const char* lb_status_string(int status)
+{
+    switch (status) {
+    case LB_OK: return "ok";
+    case LB_ERR_ARG: return "invalid argument";
+    case LB_ERR_SIZE: return "size limit or workspace too small";
+    case LB_ERR_HIP: return "HIP runtime error";
+    case LB_ERR_NONFINITE: return "non-finite value detected";
+    case LB_ERR_CAPACITY: return "capacity exceeded";
+    case LB_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* lb_last_error(const lb_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int64_t lb_steps_taken(const lb_ctx* c) { return c ? c->steps : -1; }
+
+int lb_kernel_timing(lb_ctx* c, int enable)
+{
+    if (!c) return LB_ERR_ARG;
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return LB_OK;
+}
+
+int lb_kernel_time(lb_ctx* c, double* total_ms, int64_t* launches)
+{
+    if (!c || !total_ms || !launches) return LB_ERR_ARG;
+    int r = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (r) return r;
+    double ms = 0.0;
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float t = 0.0f;
+        r = hip_check(c, hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "hipEventElapsedTime");
+        if (r) return r;
+        ms += t;
+    }
+    *total_ms = ms;
+    *launches = c->timed_launches;
+    return LB_OK;
+}
+
+int lb_expand_multipoles(int64_t n, const int32_t* type, const double* center, const double* axis, const double* e1,
+                         const double* strength, double sep, int64_t* n_out, double* pos_out, double* force_out)
+{
+    if (n < 0 || !n_out) return LB_ERR_ARG;
+    if (n > 0 && (!type || !center || !axis || !strength || !pos_out || !force_out)) return LB_ERR_ARG;
+    int64_t m = 0;
+    auto put = [&](const double* R, double dr0, double dr1, double dr2, double f0, double f1, double f2) {
+        pos_out[3 * m] = R[0] + dr0;
+        pos_out[3 * m + 1] = R[1] + dr1;
+        pos_out[3 * m + 2] = R[2] + dr2;
+        force_out[3 * m] = f0;
+        force_out[3 * m + 1] = f1;
+        force_out[3 * m + 2] = f2;
+        ++m;
+    };
+    const double h = 0.5 * sep;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* R = center + 3 * i;
+        const double* a = axis + 3 * i;
+        const double s = strength[i];
+        if (type[i] == 0) {
+            put(R, 0, 0, 0, s * a[0], s * a[1], s * a[2]);
+        } else if (type[i] == 1) {
+            put(R, h * a[0], h * a[1], h * a[2], s * a[0], s * a[1], s * a[2]);
+            put(R, -h * a[0], -h * a[1], -h * a[2], -s * a[0], -s * a[1], -s * a[2]);
+        } else if (type[i] == 2) {
+            if (!e1) return LB_ERR_ARG;
+            const double* u = e1 + 3 * i;
+            const double v[3] = {a[1] * u[2] - a[2] * u[1], a[2] * u[0] - a[0] * u[2], a[0] * u[1] - a[1] * u[0]};
+            put(R, h * u[0], h * u[1], h * u[2], s * v[0], s * v[1], s * v[2]);
+            put(R, -h * u[0], -h * u[1], -h * u[2], -s * v[0], -s * v[1], -s * v[2]);
+            put(R, h * v[0], h * v[1], h * v[2], -s * u[0], -s * u[1], -s * u[2]);
+            put(R, -h * v[0], -h * v[1], -h * v[2], s * u[0], s * u[1], s * u[2]);
+        } else {
+            return LB_ERR_ARG;
+        }
+    }
+    *n_out = m;
+    return LB_OK;
+}
+
+}  // extern "C"

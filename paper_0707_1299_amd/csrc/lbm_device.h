@@ -1,0 +1,128 @@
+// Device-side definitions shared by the liblbm kernels (gfx950).
+//
+// Velocity set: D3Q19 (the DdQn quadrature of Sec. II with the standard
+// 19-velocity set), listed here as rest, the six faces and the twelve edges,
+// each followed by its opposite.  Weights 1/3, 1/18, 1/36; c_s^2 = 1/3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int NQ = 19;
+constexpr int BLOCK = 256;  // threads per block of the lattice kernels (4 wave64s)
+
+__host__ __device__ constexpr int cvel(int i, int a)
+{
+    constexpr int t[NQ][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                              {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+                              {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    return t[i][a];
+}
+
+__host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+enum Storage { ST_FP64 = 0, ST_FP32 = 1, ST_FP16 = 2 };
+
+template <int ST> struct StoreT;
+template <> struct StoreT<ST_FP64> { using S = double; using T = double; };
+template <> struct StoreT<ST_FP32> { using S = float; using T = float; };
+template <> struct StoreT<ST_FP16> { using S = _Float16; using T = float; };
+
+// Per-point record rebuilt before every step that needs it: base node of the
+// 4-wide stencil (floor(R) - 1, wrapped), the three sets of one-dimensional
+// kernel weights, and the force, in the arithmetic type of the storage mode.
+template <class T> struct alignas(16) PRec {
+    int bx, by, bz, box;
+    T wx[4], wy[4], wz[4];
+    T f[3];
+    T pad;
+};
+
+// Per-box parameters read by the step kernels.
+struct alignas(16) BoxDev {
+    double tau;
+    double omega;      // 1 / (tau + 1/2)
+    double gc[3];      // uniform counter-force density (zero unless requested)
+    float s_in;        // FP16: dequantise multiplier 2^-e of the stored data
+    float s_out;       // FP16: quantise multiplier 2^e of the data written this step
+    int e_data;        // FP16: exponent of the data currently stored
+    unsigned maxbits;  // FP16: max |bracket| of the last step (float bits)
+    int nonfinite;     // sticky: non-finite value or FP16 overflow seen
+    int pad;
+};
+
+// Geometry of the lattice and its tiles (all boxes share it).
+struct Geom {
+    int nx, ny, nz, nboxes;
+    int tx, ty, tz;       // tile extent per axis (tx * ty * tz == BLOCK)
+    int ntx, nty, ntz;    // tiles per axis
+    int maxp;             // max tiles touched by one point's stencil
+    int pad;
+    long long N;          // nodes per box
+    long long sp;         // elements between population planes
+    long long sbox;       // elements between boxes (NQ * sp)
+    long long tiles_per_box;
+    long long ntiles;
+    double rho0;
+};
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD
+// works through a contiguous run of tiles (neighbouring tiles share cache
+// lines of the x-shifted pulls and are then served by the same L2).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int xcd = b & 7, j = b >> 3;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
+}
+
+// One-dimensional weight of a stencil whose first node is `base` at node
+// coordinate `x` on a periodic axis of length n.
+template <class T>
+__device__ __forceinline__ T stencil_w(int x, int base, int n, const T (&w)[4])
+{
+    int d = x - base;
+    if (d < 0) d += n;
+    return d == 0 ? w[0] : d == 1 ? w[1] : d == 2 ? w[2] : d == 3 ? w[3] : T(0);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Peskin's 4-point kernel at the four nodes floor(r)-1 .. floor(r)+2 for a
+// point at fractional offset f = r - floor(r) in [0, 1): Eq. deltadef at
+// distances 1+f, f, 1-f, 2-f, which share the root q = sqrt(1 + 4f - 4f^2).
+__device__ __forceinline__ void peskin4(double f, double (&w)[4])
+{
+    const double q = sqrt(1.0 + 4.0 * f - 4.0 * f * f);
+    w[0] = (3.0 - 2.0 * f - q) * 0.125;
+    w[1] = (3.0 - 2.0 * f + q) * 0.125;
+    w[2] = (1.0 + 2.0 * f + q) * 0.125;
+    w[3] = (1.0 + 2.0 * f - q) * 0.125;
+}
+
+// Wrap r into [0, L).
+__device__ __forceinline__ double wrap_pos(double r, double L)
+{
+    r -= L * floor(r / L);
+    if (r >= L) r -= L;
+    if (r < 0.0) r = 0.0;
+    return r;
+}
+
+}  // namespace lbm

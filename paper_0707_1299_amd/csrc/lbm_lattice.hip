@@ -1,0 +1,382 @@
+// Lattice kernels: the fused forced-MRT step and the moment / diagnostic
+// passes that share its per-node arithmetic.
+//
+// One thread per node, one 256-thread block per tile of TX x TY x TZ nodes
+// (x fastest, one wave64 per x-row segment).  The step is a pull scheme:
+// node x gathers population i from x - c_i of the source copy (the
+// propagation of Sec. II), collides in registers and writes its own 19
+// post-collision populations to the destination copy.  Populations are kept
+// as deviations from w_i rho0; the FP16 mode stores (deviation / w_i) * 2^e.
+//
+// Collision, per node (Eq. fiexp and the A, B that follow it; ghosts projected
+// out, every stress mode relaxed with omega = 1/(tau + 1/2)):
+//   drho = sum df_i,  j = sum df_i c_i,  S = sum df_i (c_i c_i - I/3)
+//   rho = rho0 + drho,  u = (j + g/2) / rho              (Eq. macrovariables2)
+//   A = j + g
+//   B = S - omega (S - rho u u - tau (u g + g u))       (sign from Eq. mrtlbe)
+//   df*_i = w_i [ drho + 3 A.c_i + 9/2 B:(c_i c_i - I/3) ]
+// g is the force density spread from the tile's points with the Peskin kernel
+// (Sec. III) plus the optional uniform counter-force; u feeds the per-(tile,
+// point) interpolation partial sums of Sec. IV.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+enum Mode { M_STEP = 0, M_MOMENTS = 1, M_DIAG = 2 };
+
+constexpr int CHUNK = 32;  // points reduced per LDS round in the interpolation
+
+template <class S> __device__ __forceinline__ S ld(const S* p) { return __builtin_nontemporal_load(p); }
+
+template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_nontemporal_store(v, p); }
+
+template <int ST, int TX, int TY, int TZ, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
+                                                   typename StoreT<ST>::S* __restrict__ dst,
+                                                   BoxDev* __restrict__ boxes, const int* __restrict__ toff,
+                                                   const int* __restrict__ tlist,
+                                                   const PRec<typename StoreT<ST>::T>* __restrict__ rec,
+                                                   double* __restrict__ out0, double* __restrict__ out1)
+{
+    using S = typename StoreT<ST>::S;
+    using T = typename StoreT<ST>::T;
+    static_assert(TX * TY * TZ == BLOCK, "one node per thread");
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int t = tile;
+    const int itx = t % G.ntx;
+    t /= G.ntx;
+    const int ity = t % G.nty;
+    t /= G.nty;
+    const int itz = t % G.ntz;
+    const int box = t / G.ntz;
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int x0 = itx * TX + lx, y0 = ity * TY + ly, z0 = itz * TZ + lz;
+    const bool valid = (x0 < G.nx) & (y0 < G.ny) & (z0 < G.nz);
+    // threads past a ragged edge work on a clamped in-range node and contribute nothing
+    const int x = min(x0, G.nx - 1), y = min(y0, G.ny - 1), z = min(z0, G.nz - 1);
+    const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x + 1 == G.nx ? 0 : x + 1;
+    const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y + 1 == G.ny ? 0 : y + 1;
+    const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z + 1 == G.nz ? 0 : z + 1;
+
+    const BoxDev& B = boxes[box];
+    const S* sb = src + (long long)box * G.sbox;
+
+    // ---- pull: population i at x comes from x - c_i
+    T f[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
+        const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
+        const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
+        const S v = ld(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
+        if constexpr (ST == ST_FP16)
+            f[i] = float(v) * float(wgt(i));
+        else
+            f[i] = v;
+    }
+
+    // ---- moments (10 values)
+    T drho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const T v = f[i];
+        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+        drho += v;
+        if (cx != 0) { jx += cx > 0 ? v : -v; pxx += v; }
+        if (cy != 0) { jy += cy > 0 ? v : -v; pyy += v; }
+        if (cz != 0) { jz += cz > 0 ? v : -v; pzz += v; }
+        if (cx * cy != 0) pxy += cx * cy > 0 ? v : -v;
+        if (cx * cz != 0) pxz += cx * cz > 0 ? v : -v;
+        if (cy * cz != 0) pyz += cy * cz > 0 ? v : -v;
+    }
+    if constexpr (ST == ST_FP16) {
+        const T s = MODE == M_STEP ? T(B.s_in) : T(ldexpf(1.0f, -B.e_data));
+        drho *= s; jx *= s; jy *= s; jz *= s;
+        pxx *= s; pyy *= s; pzz *= s; pxy *= s; pxz *= s; pyz *= s;
+    }
+
+    // ---- force density at this node: counter-force + the tile's points
+    T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
+    int k0 = 0, k1 = 0;
+    if (toff) {
+        k0 = toff[tile];
+        k1 = toff[tile + 1];
+    }
+    for (int k = k0; k < k1; ++k) {
+        const PRec<T>& r = rec[tlist[k]];
+        const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
+                    stencil_w<T>(z, r.bz, G.nz, r.wz);
+        gx += r.f[0] * w;
+        gy += r.f[1] * w;
+        gz += r.f[2] * w;
+    }
+
+    const T rho = T(G.rho0) + drho;
+    const T ir = T(1) / rho;
+    const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    if constexpr (MODE == M_MOMENTS) {
+        if (valid) {
+            const long long n = ((long long)z * G.ny + y) * G.nx + x;
+            if (out0) out0[(long long)box * G.N + n] = G.rho0 + double(drho);
+            out1[((long long)box * 3 + 0) * G.N + n] = double(ux);
+            out1[((long long)box * 3 + 1) * G.N + n] = double(uy);
+            out1[((long long)box * 3 + 2) * G.N + n] = double(uz);
+        }
+        return;
+    }
+
+    if constexpr (MODE == M_DIAG) {
+        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + pxy + pxz + pyz + gx + gy + gz;
+        const bool bad = !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
+        double v[LBD_N];
+        const double X = x, Y = y, Z = z;
+        v[0] = drho; v[1] = jx; v[2] = jy; v[3] = jz;
+        v[4] = gx; v[5] = gy; v[6] = gz;
+        v[7] = Y * double(gz) - Z * double(gy);
+        v[8] = Z * double(gx) - X * double(gz);
+        v[9] = X * double(gy) - Y * double(gx);
+        v[10] = sqrt(double(ux) * ux + double(uy) * uy + double(uz) * uz);
+        v[11] = bad ? 1.0 : 0.0;
+        __shared__ double red[4][LBD_N];
+#pragma unroll
+        for (int c = 0; c < LBD_N; ++c) {
+            double a = valid ? v[c] : 0.0;
+            if (c == 10) {
+                if (!(a == a)) a = 0.0;  // max ignores NaN; the count reports it
+                a = wave_max(a);
+            } else {
+                a = wave_sum(a);
+            }
+            if (lane == 0) red[wave][c] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x < LBD_N) {
+            const int c = threadIdx.x;
+            double a;
+            if (c == 10)
+                a = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
+            else
+                a = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+            out0[(long long)tile * LBD_N + c] = a;
+        }
+        return;
+    }
+
+    // ---- M_STEP: collide
+    const T ax = jx + gx, ay = jy + gy, az = jz + gz;
+    const T third = T(1.0 / 3.0);
+    const T sxx = pxx - drho * third, syy = pyy - drho * third, szz = pzz - drho * third;
+    const T tau = T(B.tau), om = T(B.omega);
+    const T Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
+    const T Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
+    const T Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
+    const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
+    const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
+    const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
+    const T base = drho - T(1.5) * (Bxx + Byy + Bzz);
+
+    T br[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+        T a = 0, q = 0;
+        if (cx != 0) { a += cx > 0 ? ax : -ax; q += Bxx; }
+        if (cy != 0) { a += cy > 0 ? ay : -ay; q += Byy; }
+        if (cz != 0) { a += cz > 0 ? az : -az; q += Bzz; }
+        if (cx * cy != 0) q += cx * cy > 0 ? T(2) * Bxy : T(-2) * Bxy;
+        if (cx * cz != 0) q += cx * cz > 0 ? T(2) * Bxz : T(-2) * Bxz;
+        if (cy * cz != 0) q += cy * cz > 0 ? T(2) * Byz : T(-2) * Byz;
+        br[i] = base + T(3) * a + T(4.5) * q;
+    }
+
+    // ---- store the post-collision populations at this node
+    S* db = dst + (long long)box * G.sbox;
+    const long long n = ((long long)z * G.ny + y) * G.nx + x;
+    if (valid) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            if constexpr (ST == ST_FP16)
+                st(db + i * G.sp + n, S(br[i] * B.s_out));
+            else
+                st(db + i * G.sp + n, S(T(wgt(i)) * br[i]));
+        }
+    }
+
+    // ---- health: non-finite values; FP16 range and the max for rescaling
+    {
+        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
+        bool bad = valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
+        if constexpr (ST == ST_FP16) {
+            T m = 0;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) m = fmax(m, fabs(br[i]));
+            if (!valid) m = 0;
+            bad = bad || (m * B.s_out > T(65504));
+            m = wave_max(m);
+            __shared__ float wm[4];
+            if (lane == 0) wm[wave] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const float mm = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+                if (mm > 0.0f) atomicMax(&boxes[box].maxbits, __float_as_uint(mm));
+            }
+        }
+        if (__any(bad) && lane == 0) atomicOr(&boxes[box].nonfinite, 1);
+    }
+
+    // ---- interpolation partial sums: sum over this tile's nodes of u * deltaP(x - R)
+    if (k1 > k0) {
+        __shared__ T red[4][CHUNK][3];
+        for (int c0 = k0; c0 < k1; c0 += CHUNK) {
+            const int cn = min(CHUNK, k1 - c0);
+            for (int kk = 0; kk < cn; ++kk) {
+                const PRec<T>& r = rec[tlist[c0 + kk]];
+                T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
+                      stencil_w<T>(z, r.bz, G.nz, r.wz);
+                if (!valid) w = T(0);
+                T sx = 0, sy = 0, sz = 0;
+                if (__any(w != T(0))) {
+                    sx = wave_sum(ux * w);
+                    sy = wave_sum(uy * w);
+                    sz = wave_sum(uz * w);
+                }
+                if (lane == 0) {
+                    red[wave][kk][0] = sx;
+                    red[wave][kk][1] = sy;
+                    red[wave][kk][2] = sz;
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < 3 * cn) {
+                const int kk = threadIdx.x / 3, c = threadIdx.x % 3;
+                out0[(long long)(c0 + kk) * 3 + c] =
+                    ((double(red[0][kk][c]) + double(red[1][kk][c])) + double(red[2][kk][c])) + double(red[3][kk][c]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Equilibrium of Eq. eqf at (rho, u) written so that the next pull sees it at
+// every node: the copy held at node y for population i is the equilibrium of
+// node y + c_i.
+template <int ST>
+__global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename StoreT<ST>::S* __restrict__ dst,
+                                                       const BoxDev* __restrict__ boxes,
+                                                       const double* __restrict__ rho, const double* __restrict__ u)
+{
+    using S = typename StoreT<ST>::S;
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= G.N * G.nboxes) return;
+    const int box = int(gid / G.N);
+    const long long n = gid % G.N;
+    const int x = int(n % G.nx), y = int((n / G.nx) % G.ny), z = int(n / ((long long)G.nx * G.ny));
+    const double s = ST == ST_FP16 ? ldexp(1.0, boxes[box].e_data) : 1.0;
+    S* db = dst + (long long)box * G.sbox;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        int xs = x + cvel(i, 0), ys = y + cvel(i, 1), zs = z + cvel(i, 2);
+        xs = xs < 0 ? xs + G.nx : (xs >= G.nx ? xs - G.nx : xs);
+        ys = ys < 0 ? ys + G.ny : (ys >= G.ny ? ys - G.ny : ys);
+        zs = zs < 0 ? zs + G.nz : (zs >= G.nz ? zs - G.nz : zs);
+        const long long m = ((long long)zs * G.ny + ys) * G.nx + xs;
+        const double r = rho[(long long)box * G.N + m];
+        const double vx = u[((long long)box * 3 + 0) * G.N + m];
+        const double vy = u[((long long)box * 3 + 1) * G.N + m];
+        const double vz = u[((long long)box * 3 + 2) * G.N + m];
+        const double cu = cvel(i, 0) * vx + cvel(i, 1) * vy + cvel(i, 2) * vz;
+        const double uu = vx * vx + vy * vy + vz * vz;
+        const double bracket = (r - G.rho0) + 3.0 * r * cu + 4.5 * r * (cu * cu - uu / 3.0);
+        db[i * G.sp + n] = ST == ST_FP16 ? S(bracket * s) : S(wgt(i) * bracket);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+
+template <int ST, int TX, int TY, int TZ>
+static void launch_lattice_t(const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                             const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+{
+    using S = typename StoreT<ST>::S;
+    using T = typename StoreT<ST>::T;
+    const unsigned nblocks = (unsigned)G.ntiles;
+    auto a0 = (const S*)src;
+    auto a1 = (S*)dst;
+    auto r = (const PRec<T>*)rec;
+    if (mode == M_STEP)
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1, boxes,
+                           toff, tlist, r, out0, out1);
+    else if (mode == M_MOMENTS)
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_MOMENTS>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
+                           boxes, toff, tlist, r, out0, out1);
+    else
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_DIAG>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1, boxes,
+                           toff, tlist, r, out0, out1);
+}
+
+template <int ST>
+static bool launch_lattice_s(const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                             const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+{
+#define LBM_TILE(X, Y, Z)                                                                                  \
+    if (G.tx == X && G.ty == Y && G.tz == Z) {                                                             \
+        launch_lattice_t<ST, X, Y, Z>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);          \
+        return true;                                                                                       \
+    }
+    LBM_TILE(64, 2, 2)
+    LBM_TILE(64, 4, 1)
+    LBM_TILE(64, 1, 4)
+    LBM_TILE(32, 4, 2)
+    LBM_TILE(32, 2, 4)
+    LBM_TILE(16, 4, 4)
+    LBM_TILE(128, 2, 1)
+    LBM_TILE(128, 1, 2)
+    LBM_TILE(256, 1, 1)
+#undef LBM_TILE
+    return false;
+}
+
+bool tile_supported(int tx, int ty, int tz)
+{
+    const int ok[][3] = {{64, 2, 2}, {64, 4, 1}, {64, 1, 4}, {32, 4, 2}, {32, 2, 4},
+                         {16, 4, 4}, {128, 2, 1}, {128, 1, 2}, {256, 1, 1}};
+    for (auto& o : ok)
+        if (o[0] == tx && o[1] == ty && o[2] == tz) return true;
+    return false;
+}
+
+bool launch_lattice(int storage, const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                    const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+{
+    switch (storage) {
+    case ST_FP64: return launch_lattice_s<ST_FP64>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    case ST_FP32: return launch_lattice_s<ST_FP32>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    case ST_FP16: return launch_lattice_s<ST_FP16>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    }
+    return false;
+}
+
+void launch_equilibrium(int storage, const Geom& G, void* dst, const BoxDev* boxes, const double* rho,
+                        const double* u, hipStream_t s)
+{
+    const long long total = G.N * G.nboxes;
+    const unsigned nb = (unsigned)((total + BLOCK - 1) / BLOCK);
+    switch (storage) {
+    case ST_FP64:
+        hipLaunchKernelGGL(k_equilibrium<ST_FP64>, dim3(nb), dim3(BLOCK), 0, s, G, (double*)dst, boxes, rho, u);
+        break;
+    case ST_FP32:
+        hipLaunchKernelGGL(k_equilibrium<ST_FP32>, dim3(nb), dim3(BLOCK), 0, s, G, (float*)dst, boxes, rho, u);
+        break;
+    case ST_FP16:
+        hipLaunchKernelGGL(k_equilibrium<ST_FP16>, dim3(nb), dim3(BLOCK), 0, s, G, (_Float16*)dst, boxes, rho, u);
+        break;
+    }
+}
+
+}  // namespace lbm

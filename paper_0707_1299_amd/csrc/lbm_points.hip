@@ -1,0 +1,631 @@
+// Point-force kernels: per-point stencil records, deterministic binning of
+// points to the lattice tiles their stencils touch, per-box force sums and
+// FP16 exponents, the colloid update, interpolation at arbitrary points and
+// the reduction of the diagnostics.
+//
+// Spreading and interpolation use Peskin's 4-point kernel (Eq. deltadef,
+// Sec. III) over the 4x4x4 nodes floor(R)-1 .. floor(R)+2 of each point.
+// The colloid update is dR/dt = v(R) + F/(6 pi eta) (1/a - 1/a_L) (Sec. IV),
+// integrated with one explicit Euler step per lattice step.
+#include <math.h>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// Distinct tiles met by the 4 consecutive nodes base .. base+3 (periodic) of
+// one axis, in order of first appearance.
+__device__ __forceinline__ int axis_tiles(int base, int n, int tdim, int (&out)[4])
+{
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int node = base + k;
+        if (node >= n) node -= n;
+        const int t = node / tdim;
+        bool dup = false;
+        for (int j = 0; j < cnt; ++j) dup |= (out[j] == t);
+        if (!dup) out[cnt++] = t;
+    }
+    return cnt;
+}
+
+struct TileSet {
+    int tx[4], ty[4], tz[4];
+    int cx, cy, cz;
+};
+
+__device__ __forceinline__ void point_tiles(const Geom& G, int bx, int by, int bz, TileSet& s)
+{
+    s.cx = axis_tiles(bx, G.nx, G.tx, s.tx);
+    s.cy = axis_tiles(by, G.ny, G.ty, s.ty);
+    s.cz = axis_tiles(bz, G.nz, G.tz, s.tz);
+}
+
+__device__ __forceinline__ long long tile_id(const Geom& G, int box, int tz, int ty, int tx)
+{
+    return (((long long)box * G.ntz + tz) * G.nty + ty) * G.ntx + tx;
+}
+
+// ---------------------------------------------------------------------------
+// 1. records: wrapped base node, one-dimensional weights, force; count the
+//    (tile, point) pairs.  err bit 1: box id out of range, bit 2: non-finite input.
+template <class T>
+__global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long long off, const double* __restrict__ pos,
+                                              const double* __restrict__ frc, const int* __restrict__ boxid,
+                                              PRec<T>* __restrict__ rec, int* __restrict__ count,
+                                              int* __restrict__ pslot, int* __restrict__ err)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long p = off + i;
+    int box = boxid ? boxid[i] : 0;
+    if (box < 0 || box >= G.nboxes) {
+        atomicOr(err, 1);
+        box = 0;
+    }
+    double R[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double F[3] = {frc[3 * i], frc[3 * i + 1], frc[3 * i + 2]};
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) ok = ok && (fabs(R[a]) < 1e300) && (fabs(F[a]) < 1e300);
+    if (!ok) {
+        atomicOr(err, 2);
+        R[0] = R[1] = R[2] = 0.0;
+        F[0] = F[1] = F[2] = 0.0;
+    }
+    const int L[3] = {G.nx, G.ny, G.nz};
+    int base[3];
+    PRec<T> r;
+    for (int a = 0; a < 3; ++a) {
+        const double x = wrap_pos(R[a], double(L[a]));
+        int b0 = (int)floor(x);
+        if (b0 >= L[a]) b0 = L[a] - 1;
+        double w[4];
+        peskin4(x - b0, w);
+        base[a] = b0 == 0 ? L[a] - 1 : b0 - 1;
+        T* dst = a == 0 ? r.wx : (a == 1 ? r.wy : r.wz);
+        for (int k = 0; k < 4; ++k) dst[k] = T(w[k]);
+    }
+    r.bx = base[0];
+    r.by = base[1];
+    r.bz = base[2];
+    r.box = box;
+    r.f[0] = T(F[0]);
+    r.f[1] = T(F[1]);
+    r.f[2] = T(F[2]);
+    r.pad = T(0);
+    rec[p] = r;
+    for (int k = 0; k < G.maxp; ++k) pslot[p * G.maxp + k] = -1;
+    TileSet s;
+    point_tiles(G, r.bx, r.by, r.bz, s);
+    for (int iz = 0; iz < s.cz; ++iz)
+        for (int iy = 0; iy < s.cy; ++iy)
+            for (int ix = 0; ix < s.cx; ++ix) atomicAdd(&count[tile_id(G, box, s.tz[iz], s.ty[iy], s.tx[ix])], 1);
+}
+
+// ---------------------------------------------------------------------------
+// 2. exclusive scan of the per-tile counts into offsets (two passes; integer
+//    sums, so the result does not depend on the order).  The second pass also
+//    clears count and cursor for the next build.
+constexpr int SCAN_B = 1024;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total)
+{
+    // 1024 threads: wave-level inclusive scan, then scan of the 16 wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < SCAN_B / 64; ++w) {
+            const int t = sh[w];
+            sh[w] = acc;
+            acc += t;
+        }
+        sh[SCAN_B / 64] = acc;
+    }
+    __syncthreads();
+    total = sh[SCAN_B / 64];
+    const int r = sh[wave] + incl - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_sums(long long n, const int* __restrict__ count, int* __restrict__ bsum)
+{
+    __shared__ int sh[SCAN_B / 64 + 1];
+    const long long i = (long long)blockIdx.x * SCAN_B + threadIdx.x;
+    const int v = i < n ? count[i] : 0;
+    int total;
+    block_exclusive_scan(v, sh, total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restrict__ count, const int* __restrict__ bsum,
+                                                       int* __restrict__ toff, int* __restrict__ cursor)
+{
+    __shared__ int sh[SCAN_B / 64 + 1];
+    __shared__ int pre;
+    // prefix of the block sums before this block
+    int acc = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += SCAN_B) acc += bsum[b];
+    int dummy;
+    const int part = block_exclusive_scan(acc, sh, dummy);
+    (void)part;
+    if (threadIdx.x == 0) pre = dummy;
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * SCAN_B + threadIdx.x;
+    const int v = i < n ? count[i] : 0;
+    int total;
+    const int ex = block_exclusive_scan(v, sh, total);
+    if (i < n) {
+        toff[i] = pre + ex;
+        count[i] = 0;
+        cursor[i] = 0;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) toff[n] = pre + total;
+}
+
+// ---------------------------------------------------------------------------
+// 3. fill the per-tile point lists (slot order from atomics; fixed by step 4)
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, const PRec<T>* __restrict__ rec,
+                                              const int* __restrict__ toff, int* __restrict__ cursor,
+                                              int* __restrict__ tlist)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const PRec<T> r = rec[p];
+    TileSet s;
+    point_tiles(G, r.bx, r.by, r.bz, s);
+    for (int iz = 0; iz < s.cz; ++iz)
+        for (int iy = 0; iy < s.cy; ++iy)
+            for (int ix = 0; ix < s.cx; ++ix) {
+                const long long t = tile_id(G, r.box, s.tz[iz], s.ty[iy], s.tx[ix]);
+                const int slot = toff[t] + atomicAdd(&cursor[t], 1);
+                tlist[slot] = (int)p;
+            }
+}
+
+// 4. sort every tile's list by point index (so sums run in a fixed order) and
+//    record, for each point and each tile it touches, where it sits in that
+//    tile's list.
+template <class T>
+__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const PRec<T>* __restrict__ rec,
+                                                    const int* __restrict__ toff, int* __restrict__ tlist,
+                                                    int* __restrict__ pslot)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G.ntiles) return;
+    const int a = toff[t], b = toff[t + 1];
+    if (a == b) return;
+    for (int i = a + 1; i < b; ++i) {
+        const int v = tlist[i];
+        int j = i - 1;
+        while (j >= a && tlist[j] > v) {
+            tlist[j + 1] = tlist[j];
+            --j;
+        }
+        tlist[j + 1] = v;
+    }
+    // this tile's coordinates
+    long long q = t;
+    const int itx = int(q % G.ntx);
+    q /= G.ntx;
+    const int ity = int(q % G.nty);
+    q /= G.nty;
+    const int itz = int(q % G.ntz);
+    for (int i = a; i < b; ++i) {
+        const int p = tlist[i];
+        const PRec<T> r = rec[p];
+        TileSet s;
+        point_tiles(G, r.bx, r.by, r.bz, s);
+        int jx = 0, jy = 0, jz = 0;
+        for (int k = 0; k < s.cx; ++k)
+            if (s.tx[k] == itx) jx = k;
+        for (int k = 0; k < s.cy; ++k)
+            if (s.ty[k] == ity) jy = k;
+        for (int k = 0; k < s.cz; ++k)
+            if (s.tz[k] == itz) jz = k;
+        pslot[(long long)p * G.maxp + (jz * s.cy + jy) * s.cx + jx] = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5. per-box work before a step: the counter-force density -sum F / N and, for
+//    FP16 storage, the exponent of the data written by the coming step, chosen
+//    from the largest bracket of the last one.  The force sum visits each point
+//    once, in its home tile (the tile of node floor(R)), over the box's own
+//    tiles in a fixed chunking, so the result does not depend on how many
+//    boxes share the launch or on the order the bins were filled.
+constexpr int BOX_CHUNKS = 64;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>* __restrict__ rec,
+                                                    const int* __restrict__ toff, const int* __restrict__ tlist,
+                                                    double* __restrict__ part, unsigned* __restrict__ ticket,
+                                                    BoxDev* __restrict__ boxes, int zero_net, int fp16_exp)
+{
+    const int b = blockIdx.x, c = blockIdx.y, C = gridDim.y;
+    if (zero_net) {
+        double s[3] = {0.0, 0.0, 0.0};
+        if (toff) {
+            const long long lo = G.tiles_per_box * c / C, hi = G.tiles_per_box * (c + 1) / C;
+            for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+                const long long tt = (long long)b * G.tiles_per_box + t;
+                for (int k = toff[tt]; k < toff[tt + 1]; ++k) {
+                    const PRec<T>& r = rec[tlist[k]];
+                    int hx = r.bx + 1, hy = r.by + 1, hz = r.bz + 1;
+                    if (hx == G.nx) hx = 0;
+                    if (hy == G.ny) hy = 0;
+                    if (hz == G.nz) hz = 0;
+                    const long long home = (((long long)r.box * G.ntz + hz / G.tz) * G.nty + hy / G.ty) * G.ntx + hx / G.tx;
+                    if (home == tt) {
+                        s[0] += double(r.f[0]);
+                        s[1] += double(r.f[1]);
+                        s[2] += double(r.f[2]);
+                    }
+                }
+            }
+        }
+        __shared__ double red[4][3];
+        __shared__ int last;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int k = 0; k < 3; ++k) {
+            const double v = wave_sum(s[k]);
+            if (lane == 0) red[wave][k] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 3; ++k)
+                part[((long long)b * C + c) * 3 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+            __threadfence();
+            last = (atomicAdd(&ticket[b], 1u) == unsigned(C - 1));
+        }
+        __syncthreads();
+        if (last && threadIdx.x == 0) {
+            __threadfence();
+            double tot[3] = {0.0, 0.0, 0.0};
+            for (int j = 0; j < C; ++j)
+                for (int k = 0; k < 3; ++k) tot[k] += ((volatile double*)part)[((long long)b * C + j) * 3 + k];
+            for (int k = 0; k < 3; ++k) boxes[b].gc[k] = -tot[k] / double(G.N);
+            ticket[b] = 0u;
+        }
+    }
+    if (fp16_exp && c == 0 && threadIdx.x == 0) {
+        BoxDev& B = boxes[b];
+        const int e_in = B.e_data;
+        const float m = __uint_as_float(B.maxbits);
+        int e_out = e_in;
+        if (m > 0.0f && m < 3.0e38f) {
+            const float v = ldexpf(m, e_in);
+            if (v > 32768.0f || v < 4096.0f) e_out = 13 - ilogbf(m);
+        }
+        e_out = max(-100, min(120, e_out));
+        B.s_in = ldexpf(1.0f, -e_in);
+        B.s_out = ldexpf(1.0f, e_out);
+        B.e_data = e_out;
+        B.maxbits = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 6. interpolated velocity of each point (sum of its tile partials in a fixed
+//    order), optional outputs, and the colloid update with the optional MLP
+//    correction to 1/a_L.
+struct AdvectArgs {
+    long long n, off;
+    const double* frc;
+    double* pos;
+    double* vel_out;
+    double* vel_sum;
+    const int* boxid;
+    double inv_a, inv_aL;
+    const uint16_t* mlp;
+    float in_shift[4], in_scale[4], out_scale;
+    int advect;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// 4 -> 64 tanh -> 64 tanh -> 1 with the weights staged in LDS as FP32
+__device__ float mlp_eval(const float* __restrict__ W, const float (&xin)[4])
+{
+    const float* W1 = W;
+    const float* b1 = W1 + 256;
+    const float* W2 = b1 + 64;
+    const float* b2 = W2 + 4096;
+    const float* W3 = b2 + 64;
+    const float* b3 = W3 + 64;
+    float h1[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        float s = b1[j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = fmaf(W1[j * 4 + k], xin[k], s);
+        h1[j] = tanhf(s);
+    }
+    float y = b3[0];
+    for (int j = 0; j < 64; ++j) {
+        float s = b2[j];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) s = fmaf(W2[j * 64 + k], h1[k], s);
+        y = fmaf(W3[j], tanhf(s), y);
+    }
+    return y;
+}
+
+__global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
+                                                const int* __restrict__ pslot, const double* __restrict__ partial)
+{
+    __shared__ float W[LBML_NPARAM_DEV];
+    if (A.mlp) {
+        for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) W[k] = bf16_to_f32(A.mlp[k]);
+        __syncthreads();
+    }
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const long long p = A.off + i;
+    double U[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < G.maxp; ++k) {
+        const int s = pslot[p * G.maxp + k];
+        if (s >= 0) {
+            U[0] += partial[3LL * s];
+            U[1] += partial[3LL * s + 1];
+            U[2] += partial[3LL * s + 2];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        if (A.vel_out) A.vel_out[3 * i + c] = U[c];
+        if (A.vel_sum) A.vel_sum[3 * i + c] += U[c];
+    }
+    if (!A.advect) return;
+    int box = A.boxid ? A.boxid[i] : 0;
+    if (box < 0 || box >= G.nboxes) box = 0;
+    const double tau = boxes[box].tau;
+    const double eta = G.rho0 * tau / 3.0;
+    double inv_aL = A.inv_aL;
+    double R[3] = {A.pos[3 * i], A.pos[3 * i + 1], A.pos[3 * i + 2]};
+    const double L[3] = {double(G.nx), double(G.ny), double(G.nz)};
+    if (A.mlp) {
+        float xin[4];
+        for (int a = 0; a < 3; ++a) {
+            const double r = wrap_pos(R[a], L[a]);
+            xin[a] = (float(r - floor(r)) - A.in_shift[a]) * A.in_scale[a];
+        }
+        xin[3] = (float(tau) - A.in_shift[3]) * A.in_scale[3];
+        inv_aL += double(A.out_scale) * double(mlp_eval(W, xin));
+    }
+    const double mob = (A.inv_a - inv_aL) / (6.0 * M_PI * eta);
+    for (int a = 0; a < 3; ++a) A.pos[3 * i + a] = wrap_pos(R[a] + U[a] + A.frc[3 * i + a] * mob, L[a]);
+}
+
+// ---------------------------------------------------------------------------
+// 7. interpolation at arbitrary points: one wave per point, one lane per
+//    stencil node; each lane rebuilds u at its node from the stored
+//    populations and the binned forces.
+template <int ST>
+__global__ __launch_bounds__(256) void k_interp_points(const Geom G, long long n, const double* __restrict__ pos,
+                                                       const int* __restrict__ boxid, double* __restrict__ out,
+                                                       const typename StoreT<ST>::S* __restrict__ src,
+                                                       const BoxDev* __restrict__ boxes, const int* __restrict__ toff,
+                                                       const int* __restrict__ tlist,
+                                                       const PRec<typename StoreT<ST>::T>* __restrict__ rec)
+{
+    using T = typename StoreT<ST>::T;
+    const int lane = threadIdx.x & 63;
+    const long long q = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (q >= n) return;
+    int box = boxid ? boxid[q] : 0;
+    if (box < 0 || box >= G.nboxes) box = 0;
+    const int d[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int L[3] = {G.nx, G.ny, G.nz};
+    int node[3];
+    double wt = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        const double x = wrap_pos(pos[3 * q + a], double(L[a]));
+        int b0 = (int)floor(x);
+        if (b0 >= L[a]) b0 = L[a] - 1;
+        double w[4];
+        peskin4(x - b0, w);
+        int nd = b0 - 1 + d[a];
+        if (nd < 0) nd += L[a];
+        if (nd >= L[a]) nd -= L[a];
+        node[a] = nd;
+        wt *= w[d[a]];
+    }
+    const int x = node[0], y = node[1], z = node[2];
+    const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x + 1 == G.nx ? 0 : x + 1;
+    const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y + 1 == G.ny ? 0 : y + 1;
+    const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z + 1 == G.nz ? 0 : z + 1;
+    const auto* sb = src + (long long)box * G.sbox;
+    const BoxDev& B = boxes[box];
+    T drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
+        const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
+        const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
+        T v = T(sb[i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx]);
+        if constexpr (ST == ST_FP16) v *= T(wgt(i));
+        drho += v;
+        if (cvel(i, 0) != 0) jx += cvel(i, 0) > 0 ? v : -v;
+        if (cvel(i, 1) != 0) jy += cvel(i, 1) > 0 ? v : -v;
+        if (cvel(i, 2) != 0) jz += cvel(i, 2) > 0 ? v : -v;
+    }
+    if constexpr (ST == ST_FP16) {
+        const T s = T(ldexpf(1.0f, -B.e_data));
+        drho *= s;
+        jx *= s;
+        jy *= s;
+        jz *= s;
+    }
+    T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
+    if (toff) {
+        const long long t = tile_id(G, box, z / G.tz, y / G.ty, x / G.tx);
+        for (int k = toff[t]; k < toff[t + 1]; ++k) {
+            const PRec<T>& r = rec[tlist[k]];
+            const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
+                        stencil_w<T>(z, r.bz, G.nz, r.wz);
+            gx += r.f[0] * w;
+            gy += r.f[1] * w;
+            gz += r.f[2] * w;
+        }
+    }
+    const T rho = T(G.rho0) + drho;
+    const T ir = T(1) / rho;
+    const double u[3] = {double((jx + T(0.5) * gx) * ir), double((jy + T(0.5) * gy) * ir),
+                         double((jz + T(0.5) * gz) * ir)};
+    for (int c = 0; c < 3; ++c) {
+        const double s = wave_sum(wt * u[c]);
+        if (lane == 0) out[3 * q + c] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 8. diagnostics: per-box reduction of the per-tile partials in tile order
+__global__ __launch_bounds__(256) void k_diag_reduce(const Geom G, const double* __restrict__ part,
+                                                     double* __restrict__ out)
+{
+    const int b = blockIdx.x;
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = 0; c < LBD_N; ++c) {
+        double a = 0.0;
+        for (long long t = threadIdx.x; t < G.tiles_per_box; t += blockDim.x) {
+            const double v = part[((long long)b * G.tiles_per_box + t) * LBD_N + c];
+            a = c == 10 ? fmax(a, v) : a + v;
+        }
+        a = c == 10 ? wave_max(a) : wave_sum(a);
+        if (lane == 0) red[wave] = a;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            out[(long long)b * LBD_N + c] =
+                c == 10 ? fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) : ((red[0] + red[1]) + red[2]) + red[3];
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, long long n, uint32_t v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_fill_u32(void* p, long long n, uint32_t v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, s, (uint32_t*)p, n, v);
+}
+
+void launch_prep(int storage, const Geom& G, long long n, long long off, const double* pos, const double* frc,
+                 const int* boxid, void* rec, int* count, int* pslot, int* err, hipStream_t s)
+{
+    if (n <= 0) return;
+    if (storage == ST_FP64)
+        hipLaunchKernelGGL(k_prep<double>, dim3(nblk(n, 256)), dim3(256), 0, s, G, n, off, pos, frc, boxid,
+                           (PRec<double>*)rec, count, pslot, err);
+    else
+        hipLaunchKernelGGL(k_prep<float>, dim3(nblk(n, 256)), dim3(256), 0, s, G, n, off, pos, frc, boxid,
+                           (PRec<float>*)rec, count, pslot, err);
+}
+
+long long scan_blocks(long long ntiles) { return (ntiles + SCAN_B - 1) / SCAN_B; }
+
+void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
+                 int* cursor, int* tlist, int* pslot, hipStream_t s)
+{
+    const unsigned nb = (unsigned)scan_blocks(G.ntiles);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, (const int*)count, bsum);
+    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, count, (const int*)bsum, toff, cursor);
+    if (npts <= 0) return;
+    if (storage == ST_FP64) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts,
+                           (const PRec<double>*)rec, (const int*)toff, cursor, tlist);
+        hipLaunchKernelGGL(k_sort_slots<double>, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G,
+                           (const PRec<double>*)rec, (const int*)toff, tlist, pslot);
+    } else {
+        hipLaunchKernelGGL(k_fill<float>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts, (const PRec<float>*)rec,
+                           (const int*)toff, cursor, tlist);
+        hipLaunchKernelGGL(k_sort_slots<float>, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G,
+                           (const PRec<float>*)rec, (const int*)toff, tlist, pslot);
+    }
+}
+
+void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist, double* part,
+                       unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s)
+{
+    const dim3 grid(G.nboxes, zero_net ? BOX_CHUNKS : 1);
+    if (storage == ST_FP64)
+        hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, part,
+                           ticket, boxes, zero_net, fp16_exp);
+    else
+        hipLaunchKernelGGL(k_box_update<float>, grid, dim3(256), 0, s, G, (const PRec<float>*)rec, toff, tlist, part,
+                           ticket, boxes, zero_net, fp16_exp);
+}
+
+int box_chunks() { return BOX_CHUNKS; }
+
+void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, const int* pslot, const double* partial,
+                   hipStream_t s)
+{
+    if (a.n <= 0) return;
+    AdvectArgs A;
+    A.n = a.n;
+    A.off = a.off;
+    A.frc = a.frc;
+    A.pos = a.pos;
+    A.vel_out = a.vel_out;
+    A.vel_sum = a.vel_sum;
+    A.boxid = a.boxid;
+    A.inv_a = a.inv_a;
+    A.inv_aL = a.inv_aL;
+    A.mlp = a.mlp;
+    for (int k = 0; k < 4; ++k) {
+        A.in_shift[k] = a.in_shift[k];
+        A.in_scale[k] = a.in_scale[k];
+    }
+    A.out_scale = a.out_scale;
+    A.advect = a.advect;
+    hipLaunchKernelGGL(k_advect, dim3(nblk(a.n, 256)), dim3(256), 0, s, G, A, boxes, pslot, partial);
+}
+
+void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,
+                          const void* src, const BoxDev* boxes, const int* toff, const int* tlist, const void* rec,
+                          hipStream_t s)
+{
+    if (n <= 0) return;
+    const unsigned nb = nblk(n, 4);
+    switch (storage) {
+    case ST_FP64:
+        hipLaunchKernelGGL(k_interp_points<ST_FP64>, dim3(nb), dim3(256), 0, s, G, n, pos, boxid, out,
+                           (const double*)src, boxes, toff, tlist, (const PRec<double>*)rec);
+        break;
+    case ST_FP32:
+        hipLaunchKernelGGL(k_interp_points<ST_FP32>, dim3(nb), dim3(256), 0, s, G, n, pos, boxid, out,
+                           (const float*)src, boxes, toff, tlist, (const PRec<float>*)rec);
+        break;
+    case ST_FP16:
+        hipLaunchKernelGGL(k_interp_points<ST_FP16>, dim3(nb), dim3(256), 0, s, G, n, pos, boxid, out,
+                           (const _Float16*)src, boxes, toff, tlist, (const PRec<float>*)rec);
+        break;
+    }
+}
+
+void launch_diag_reduce(const Geom& G, const double* part, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diag_reduce, dim3(G.nboxes), dim3(256), 0, s, G, part, out);
+}
+
+}  // namespace lbm

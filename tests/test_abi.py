@@ -1,0 +1,86 @@
+"""The C-ABI library loads and exports every entry point include/lbm.h declares;
+host-only calls (workspace sizing, argument checks, status strings and the
+multipole helper) behave as documented.  No GPU work is launched here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+lbm = pytest.importorskip("paper_0707_1299_amd.lbm", reason="liblbm.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b((?:lb|lbml)_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_documented_calls():
+    names = declared_functions()
+    for required in ("lb_init", "lb_add_point_forces", "lb_step", "lb_moments", "lb_interp_velocity",
+                     "lb_workspace_bytes", "lb_diagnostics", "lb_sync", "lb_destroy", "lb_status_string",
+                     "lb_last_error", "lbml_forward", "lbml_loss_grad", "lbml_adam_step"):
+        assert required in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_symbol_exported(name):
+    lib = ctypes.CDLL(lbm.LIB_PATH)
+    assert hasattr(lib, name)
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True).stdout
+    assert re.search(r"\bT %s$" % name, out, flags=re.M)
+
+
+def test_workspace_bytes_pure_and_monotone():
+    a = lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "fp32"))
+    b = lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "fp64"))
+    c = lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "fp16"))
+    d = lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "fp32", max_points=1000))
+    assert c < a < b and d > a
+    # two population copies of 19 planes dominate
+    assert a >= 2 * 19 * 32 ** 3 * 4
+    assert lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "fp32")) == a
+
+
+@pytest.mark.parametrize("kw", [
+    dict(shape=(3, 32, 32)), dict(shape=(32, 32, 2)), dict(nboxes=0), dict(storage=7),
+    dict(max_points=-1), dict(tile=(64, 3, 1)),
+])
+def test_bad_params_rejected(kw):
+    args = dict(shape=(16, 16, 16), storage="fp32")
+    args.update(kw)
+    p = lbm.make_params(**args)
+    with pytest.raises(lbm.LBError) as e:
+        lbm.lb_workspace_bytes(p)
+    assert e.value.status in (lbm.LB_ERR_ARG, lbm.LB_ERR_SIZE)
+
+
+def test_status_strings():
+    for code in (lbm.LB_OK, lbm.LB_ERR_ARG, lbm.LB_ERR_SIZE, lbm.LB_ERR_HIP, lbm.LB_ERR_NONFINITE,
+                 lbm.LB_ERR_CAPACITY, lbm.LB_ERR_STATE):
+        s = lbm.lb_status_string(code)
+        assert s and s != "unknown status"
+    assert lbm.lb_status_string(12345) == "unknown status"
+
+
+def test_expand_multipoles_matches_oracle():
+    from oracle import multipole
+    from paper_0707_1299_amd import workloads
+    w = workloads.singularities(L=64, n=40)
+    pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
+    opos, ofrc = multipole.expand(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
+    assert pos.shape == opos.shape
+    assert np.abs(pos - opos).max() < 1e-13
+    assert np.abs(frc - ofrc).max() < 1e-20
+
+
+def test_expand_multipoles_rejects_unknown_type():
+    with pytest.raises(lbm.LBError):
+        lbm.lb_expand_multipoles([5], np.zeros((1, 3)), np.ones((1, 3)), np.ones((1, 3)), [1.0], 2.0)

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Norm: max over nodes and components of |u_gpu - u_oracle| divided by
+max |u_oracle| (velocity field), and the same for interpolated velocities.
+Bars: 1e-10 for FP64 storage, 1e-5 for FP32 storage.  Both sides start from
+rest (or the same equilibrium) and receive the same seeded point forces.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0707_1299_amd import lbm, workloads  # noqa: E402
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def run_gpu(shape, storage, tau, sets, steps, zero_net=False, tile=None, nboxes=1, step_chunks=None):
+    """sets: list of (pos, force, kind, model_kwargs, box).  Returns (lat, u, per-set outputs)."""
+    npts = sum(len(s[0]) for s in sets)
+    lat = lbm.Lattice(shape, storage, nboxes=nboxes, tau=tau, zero_net_force=zero_net, max_points=max(npts, 1),
+                      tile=tile)
+    outs = []
+    for pos, frc, kind, mkw, box in sets:
+        p, f = dev(pos), dev(frc)
+        vel = torch.zeros_like(p)
+        model = lbm.PointModel(vel_out=vel, **(mkw or {}))
+        b = None if box is None else dev(box, torch.int32)
+        lat.add_point_forces(p, f, b, kind, model)
+        outs.append((p, vel))
+    for n in (step_chunks or [steps]):
+        lat.step(n)
+    _, u = lat.moments(rho=False)
+    lat.sync()
+    return lat, u.cpu().numpy(), outs
+
+
+def run_oracle(shape, tau, sets, steps, zero_net=False):
+    box = oracle.Box(shape, tau, 1.0, zero_net_force=zero_net)
+    box.sets = []
+    for pos, frc, kind, mkw, _ in sets:
+        mkw = mkw or {}
+        box.sets.append(oracle.ForceSet(np.array(pos, float), np.array(frc, float),
+                                        kind="colloid" if kind == lbm.LB_COLLOIDS else "static",
+                                        inv_a=mkw.get("inv_a", 0.0), inv_aL=mkw.get("inv_aL", 0.0)))
+    box.step(steps)
+    _, u = box.moments()
+    return box, u
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_stokeslet_32cubed_500_steps(storage):
+    """32^3, rho0 = 1 at rest, tau = 1/2 (nu = 1/6), one Stokeslet F = 1e-5 z, 500 steps."""
+    pos, frc = workloads.stokeslet_box(32)
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    lat, u, outs = run_gpu((32, 32, 32), storage, 0.5, sets, 500)
+    box, uo = run_oracle((32, 32, 32), 0.5, sets, 500)
+    e = rel(u[0], uo)
+    print("stokeslet %s rel err %.3e" % (storage, e))
+    assert e <= TOL[storage]
+    # interpolated velocity at the force, last step
+    U = outs[0][1].cpu().numpy()
+    assert rel(U, box.sets[0].U) <= TOL[storage] * 10
+
+
+@pytest.mark.parametrize("storage,tile", [("fp64", None), ("fp64", (16, 4, 4)), ("fp32", (32, 2, 4)),
+                                          ("fp64", (64, 1, 4)), ("fp32", (128, 2, 1))])
+def test_ragged_multi_tile_forces_zero_net(storage, tile):
+    """Non-cubic box with ragged tiles on every axis, forces near the periodic seams."""
+    shape = (13, 10, 70)
+    g = np.random.default_rng(7)
+    pos = g.uniform(0, 1, (6, 3)) * np.array([70, 10, 13])
+    pos[0] = [69.7, 0.2, 12.9]
+    pos[1] = [0.01, 9.99, 0.5]
+    frc = g.normal(scale=1e-5, size=(6, 3))
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    lat, u, outs = run_gpu(shape, storage, 0.8, sets, 60, zero_net=True, tile=tile)
+    box, uo = run_oracle(shape, 0.8, sets, 60, zero_net=True)
+    e = rel(u[0], uo)
+    print("ragged %s %s rel err %.3e" % (storage, tile, e))
+    assert e <= TOL[storage]
+    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_multipoles(storage):
+    """Stokeslets, stresslets and rotlets expanded by the library helper."""
+    L = 40
+    w = workloads.singularities(L=L, n=12)
+    pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    lat, u, _ = run_gpu((L, L, L), storage, 0.6, sets, 120)
+    _, uo = run_oracle((L, L, L), 0.6, sets, 120)
+    e = rel(u[0], uo)
+    print("multipoles %s rel err %.3e" % (storage, e))
+    assert e <= TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_colloids_advected(storage):
+    """Sedimenting colloids: spread, interpolate, advance (a = 0.117, 1/a_L = 0.77)."""
+    shape = (24, 20, 28)
+    pos, frc = workloads.colloids(0, 12, shape=shape)
+    frc[:, 2] = -1e-4          # large enough to move the colloids visibly in 150 steps
+    model = dict(inv_a=1 / 0.117, inv_aL=0.77)
+    sets = [(pos, frc, lbm.LB_COLLOIDS, model, None)]
+    lat, u, outs = run_gpu(shape, storage, 0.7, sets, 150, zero_net=True)
+    box, uo = run_oracle(shape, 0.7, sets, 150, zero_net=True)
+    e = rel(u[0], uo)
+    R = outs[0][0].cpu().numpy()
+    dR = np.abs(R - box.sets[0].pos)
+    dR = np.minimum(dR, np.array([28, 20, 24]) - dR)
+    disp = np.abs(box.sets[0].pos - pos)
+    disp = np.minimum(disp, np.array([28, 20, 24]) - disp).max()
+    print("colloids %s u rel %.3e pos err %.3e (disp %.3e)" % (storage, e, dR.max(), disp))
+    assert e <= TOL[storage]
+    assert dR.max() <= TOL[storage] * disp
+    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_equilibrium_start_and_moments(storage):
+    """Shear wave started from the Eq. eqf equilibrium; density and velocity after 40 steps."""
+    shape = (16, 12, 20)
+    nz, ny, nx = shape
+    z = np.arange(nz)[:, None, None] * np.ones(shape)
+    x = np.arange(nx)[None, None, :] * np.ones(shape)
+    rho = 1.0 + 1e-3 * np.cos(2 * np.pi * x / nx)
+    u = np.zeros((3,) + shape)
+    u[0] = 1e-3 * np.sin(2 * np.pi * z / nz)
+    u[1] = 5e-4 * np.cos(2 * np.pi * x / nx)
+    lat = lbm.Lattice(shape, storage, tau=0.9)
+    lat.set_equilibrium(dev(rho[None]), dev(u[None]))
+    lat.step(40)
+    r, ug = lat.moments()
+    lat.sync()
+    box = oracle.Box(shape, 0.9)
+    box.df = oracle.equilibrium(rho, u, 1.0)
+    box.step(40)
+    ro, uo = box.moments()
+    assert rel(ug.cpu().numpy()[0], uo) <= TOL[storage]
+    # density deviation, relative to its own size
+    assert rel(r.cpu().numpy()[0] - 1.0, ro - 1.0) <= TOL[storage]
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_interp_velocity_at_arbitrary_points(storage):
+    shape = (20, 20, 20)
+    pos, frc = workloads.colloids(20, 5)
+    frc[:] = np.random.default_rng(3).normal(scale=1e-5, size=frc.shape)
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    lat, u, _ = run_gpu(shape, storage, 0.5, sets, 80)
+    box, uo = run_oracle(shape, 0.5, sets, 80)
+    q = np.random.default_rng(9).uniform(-5, 25, size=(50, 3))
+    Ug = lat.interp_velocity(dev(q)).cpu().numpy()
+    Uo = box.interp_velocity(q)
+    assert rel(Ug, Uo) <= TOL[storage] * 10
+
+
+def test_diagnostics_mass_momentum_force_moments():
+    shape = (16, 18, 20)
+    g = np.random.default_rng(11)
+    pos = g.uniform(3, 12, (5, 3))
+    frc = g.normal(scale=1e-5, size=(5, 3))
+    lat = lbm.Lattice(shape, "fp64", tau=0.7, max_points=5)
+    lat.add_point_forces(dev(pos), dev(frc))
+    lat.step(33)
+    r, d = lat.diagnostics()
+    assert r == lbm.LB_OK
+    d = d[0]
+    assert abs(d[0]) < 1e-15                                   # mass deviation stays 0
+    assert np.abs(d[1:4] - 33 * frc.sum(0)).max() < 1e-14      # sum jbar = n sum F
+    assert np.abs(d[4:7] - frc.sum(0)).max() < 1e-18           # sum g = sum F
+    assert np.abs(d[7:10] - np.cross(pos, frc).sum(0)).max() < 1e-15   # sum x cross g
+    assert d[11] == 0
+
+
+def test_batched_boxes_equal_single_runs_bitwise():
+    """Boxes with different tau and point counts in one launch equal one-box runs bit for bit."""
+    L = 16
+    w = workloads.mobility_boxes(nboxes=5, L=L, kmax=3)
+    taus = w["taus"]
+    for storage in ("fp32", "fp64"):
+        lat, ub, outs = run_gpu((L, L, L), storage, taus, [(w["pos"], w["force"], lbm.LB_FORCES_STATIC, None, w["box"])],
+                                70, zero_net=True, nboxes=5)
+        Ub = outs[0][1].cpu().numpy()
+        for b in range(5):
+            m = w["box"] == b
+            _, u1, o1 = run_gpu((L, L, L), storage, taus[b],
+                                [(w["pos"][m], w["force"][m], lbm.LB_FORCES_STATIC, None, None)], 70, zero_net=True)
+            assert np.array_equal(ub[b], u1[0])
+            assert np.array_equal(Ub[m], o1[0][1].cpu().numpy())
+        if storage == "fp64":
+            for b in (0, 3):
+                m = w["box"] == b
+                _, uo = run_oracle((L, L, L), taus[b], [(w["pos"][m], w["force"][m], 1, None, None)], 70, zero_net=True)
+                assert rel(ub[b], uo) <= 1e-10
+
+
+def test_graph_replay_equals_eager_and_is_deterministic():
+    pos, frc = workloads.colloids(32, 20)
+    frc[:, 2] = -1e-5
+    model = dict(inv_a=1 / 0.117, inv_aL=0.77)
+    sets = [(pos, frc, lbm.LB_COLLOIDS, model, None)]
+    _, u1, o1 = run_gpu((32, 32, 32), "fp32", 0.6, sets, 41)                       # graph + tail
+    _, u2, o2 = run_gpu((32, 32, 32), "fp32", 0.6, sets, 41, step_chunks=[3] * 13 + [2])   # eager only
+    _, u3, o3 = run_gpu((32, 32, 32), "fp32", 0.6, sets, 41)
+    assert np.array_equal(u1, u2) and np.array_equal(u1, u3)
+    assert np.array_equal(o1[0][0].cpu().numpy(), o2[0][0].cpu().numpy())
+
+
+def test_next_step_forces_apply_once():
+    shape = (12, 12, 12)
+    pos = np.array([[5.3, 6.1, 4.7]])
+    frc = np.array([[1e-5, -2e-5, 3e-5]])
+    lat = lbm.Lattice(shape, "fp64", tau=0.8, max_points=1)
+    lat.add_point_forces(dev(pos), dev(frc), kind=lbm.LB_FORCES_NEXT_STEP)
+    lat.step(9)
+    r, d = lat.diagnostics()
+    assert np.abs(d[0, 1:4] - frc[0]).max() < 1e-18           # one step's worth of momentum
+    assert np.abs(d[0, 4:7]).max() == 0.0                      # and no force registered now
+
+
+def test_invalid_box_id_reported():
+    lat = lbm.Lattice((8, 8, 8), "fp32", nboxes=2, max_points=2)
+    lat.add_point_forces(dev(np.ones((2, 3))), dev(np.ones((2, 3)) * 1e-6), dev(np.array([0, 5]), torch.int32))
+    lat.step(1)
+    with pytest.raises(lbm.LBError) as e:
+        lat.sync()
+    assert e.value.status == lbm.LB_ERR_ARG
+
+
+def test_nonfinite_force_reported():
+    lat = lbm.Lattice((8, 8, 8), "fp32", max_points=1)
+    lat.add_point_forces(dev(np.ones((1, 3))), dev(np.array([[np.nan, 0.0, 0.0]])))
+    lat.step(1)
+    with pytest.raises(lbm.LBError) as e:
+        lat.sync()
+    assert e.value.status == lbm.LB_ERR_NONFINITE
+
+
+def test_colloid_radius_constraint_rejected():
+    lat = lbm.Lattice((8, 8, 8), "fp32", max_points=1)
+    with pytest.raises(lbm.LBError) as e:
+        lat.add_point_forces(dev(np.ones((1, 3))), dev(np.ones((1, 3))), kind=lbm.LB_COLLOIDS,
+                             model=lbm.PointModel(inv_a=0.5, inv_aL=0.77))
+    assert e.value.status == lbm.LB_ERR_ARG
+
+
+def test_full_size_128_fp32_bench_configuration():
+    """The benchmark workload (128^3, FP32, 64 singularities) against the oracle over 60 steps,
+    in the launch configuration the benchmark uses (default tiles, graph replay)."""
+    L = 128
+    w = workloads.singularities(L=L, n=64)
+    pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    lat, u, outs = run_gpu((L, L, L), "fp32", 0.5, sets, 60)
+    box, uo = run_oracle((L, L, L), 0.5, sets, 60)
+    e = rel(u[0], uo)
+    print("128^3 fp32 rel err %.3e" % e)
+    assert e <= TOL["fp32"]
+    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= 1e-4
