@@ -60,10 +60,17 @@ def make_inputs(kind, shape, n):
     return pos, frc, "colloid", dict(inv_a=1 / 0.117, inv_aL=0.77)
 
 
+def tuned(shape, storage):
+    from paper_0707_1299_amd import tune
+    return tune.lookup(shape, storage) or (None, 0)
+
+
 def build_lattice(shape, storage, tau, kind, pos, frc, model):
     import torch
     from paper_0707_1299_amd import lbm
-    lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "colloid"), max_points=len(pos))
+    tile, variant = tuned(shape, storage)
+    lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "colloid"), max_points=len(pos), tile=tile,
+                      variant=variant)
     p = torch.tensor(pos, dtype=torch.float64, device="cuda")
     f = torch.tensor(frc, dtype=torch.float64, device="cuda")
     if kind == "colloid":
@@ -168,7 +175,8 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32"}[storage],
         "data": "synthetic",
         "config": {"workload": DESCR[kind] % ((shape[0], storage, n) + ((len(pos),) if kind == "singularities" else ())),
-                   "nodes": N, "points": int(len(pos)), "seed": 20261200 + (2 if kind == "singularities" else 3)},
+                   "nodes": N, "points": int(len(pos)), "seed": 20261200 + (2 if kind == "singularities" else 3),
+                   "tile": list(tuned(shape, storage)[0] or ()), "variant": tuned(shape, storage)[1]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_lattice step (fused spread/pull/collide/store/interpolate)",

@@ -82,6 +82,10 @@ typedef struct lb_params {
     int32_t tile_y;
     int32_t tile_z;
     int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default */
+    int32_t variant;        /* step-kernel variant bits (same results, different memory access):
+                               1 = x-shifted pulls as aligned loads exchanged between lanes
+                                   (needs tile_x a multiple of 64),
+                               2 = cached instead of non-temporal population loads */
 } lb_params;
 
 /*
@@ -134,9 +138,15 @@ int lb_set_equilibrium(lb_ctx* ctx, const double* d_rho, const double* d_u);
  * positions in lattice units (wrapped periodically), forces in lattice units
  * (force per step).  d_box (n) int32 names each point's box, or NULL for box 0.
  * kind is one of the LB_FORCES_ kinds or LB_COLLOIDS; model may be NULL except for colloids.
- * The arrays are read at every step that applies them and must stay valid
- * until then (stream order).  Forces spread per Sec. III; multipoles are
- * passed as their point forces (see lb_expand_multipoles).
+ * LB_FORCES_NEXT_STEP and LB_COLLOIDS arrays are read at every step that
+ * applies them; LB_FORCES_STATIC arrays are read once, before the first step
+ * after registration (re-register to change them).  All must stay valid until
+ * the work that reads them has run (stream order).  Forces spread per
+ * Sec. III; multipoles are passed as their point forces (see
+ * lb_expand_multipoles).  With FP16 storage the scale exponent follows the
+ * data with one step of delay: a jump of more than 4x in the largest
+ * population deviation within one step overflows and is reported as
+ * LB_ERR_NONFINITE.
  */
 int lb_add_point_forces(lb_ctx* ctx, int64_t n, const double* d_pos, const double* d_force,
                         const int32_t* d_box, int kind, const lb_point_model* model);

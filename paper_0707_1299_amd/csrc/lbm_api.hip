@@ -47,7 +47,8 @@ int max_axis_tiles(int n, int t)
 }
 
 struct Layout {
-    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, pslot, partial, fpart, ticket, err, diag, diagout;
+    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, pslot, partial, fpart, pmax, tmax, ticket, err, diag,
+        diagout;
     size_t total;
 };
 
@@ -83,6 +84,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_FP16) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
+    if (p->variant < 0 || p->variant > 3) { why = "unknown kernel variant"; return LB_ERR_ARG; }
     int tx, ty, tz;
     choose_tile(p, tx, ty, tz);
     if (!tile_supported(tx, ty, tz)) { why = "unsupported tile shape"; return LB_ERR_ARG; }
@@ -120,6 +122,8 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.pslot = take(sizeof(int) * P.cap * G.maxp);
     L.partial = take(sizeof(double) * 3 * P.cap * G.maxp);
     L.fpart = take(sizeof(double) * 3 * p->nboxes * P.chunks);
+    L.pmax = take(sizeof(float) * p->nboxes * P.chunks);
+    L.tmax = take(sizeof(float) * G.ntiles);
     L.ticket = take(sizeof(unsigned) * p->nboxes);
     L.err = take(sizeof(int) * 4);
     L.diag = take(sizeof(double) * LBD_N * G.ntiles);
@@ -179,6 +183,8 @@ struct lb_ctx {
     int* pslot() const { return (int*)(ws + P.L.pslot); }
     double* partial() const { return (double*)(ws + P.L.partial); }
     double* fpart() const { return (double*)(ws + P.L.fpart); }
+    float* pmax() const { return (float*)(ws + P.L.pmax); }
+    float* tmax() const { return (float*)(ws + P.L.tmax); }
     unsigned* ticket() const { return (unsigned*)(ws + P.L.ticket); }
     int* errw() const { return (int*)(ws + P.L.err); }
     double* diag() const { return (double*)(ws + P.L.diag); }
@@ -232,8 +238,8 @@ void box_update(lb_ctx* c, hipStream_t s, bool fp16_exp)
     const bool zero_net = c->p.zero_net_force != 0;
     const bool fp16 = fp16_exp && c->p.storage == LB_STORAGE_FP16;
     if (!zero_net && !fp16) return;
-    launch_box_update(c->p.storage, c->P.G, c->rec(), total_points(c) > 0 ? c->toff() : nullptr, c->tlist(),
-                      c->fpart(), c->ticket(), c->boxes(), zero_net ? 1 : 0, fp16 ? 1 : 0, s);
+    launch_box_update(c->p.storage, c->P.G, c->rec(), total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->tmax(),
+                      c->fpart(), c->pmax(), c->ticket(), c->boxes(), zero_net ? 1 : 0, fp16 ? 1 : 0, s);
 }
 
 // one step on stream s; flips c->cur
@@ -256,8 +262,8 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
         e1 = c->ev[c->ev_used++];
         (void)hipEventRecord(e0, s);
     }
-    launch_lattice(c->p.storage, G, 0, c->pop(c->cur), c->pop(c->cur ^ 1), c->boxes(), npts > 0 ? c->toff() : nullptr,
-                   c->tlist(), c->rec(), c->partial(), nullptr, s);
+    launch_lattice(c->p.storage, G, 0, c->p.variant, c->pop(c->cur), c->pop(c->cur ^ 1), c->boxes(), npts > 0 ? c->toff() : nullptr,
+                   c->tlist(), c->rec(), c->partial(), (double*)c->tmax(), s);
     if (c->timing) {
         (void)hipEventRecord(e1, s);
         c->timed_launches++;
@@ -404,6 +410,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     launch_fill_u32(c->cursor(), G.ntiles, 0u, s);
     launch_fill_u32(c->toff(), G.ntiles + 1, 0u, s);
     launch_fill_u32(c->ticket(), p->nboxes, 0u, s);
+    launch_fill_u32(c->tmax(), G.ntiles, 0u, s);
     launch_fill_u32(c->errw(), 4, 0u, s);
     r = hip_check(c, hipMemcpyAsync(c->boxes(), c->hboxes.data(), sizeof(BoxDev) * p->nboxes, hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
@@ -527,7 +534,7 @@ int lb_moments(lb_ctx* c, double* d_rho, double* d_u)
     if (!c) return LB_ERR_ARG;
     if (!d_u) return fail(c, LB_ERR_ARG, "lb_moments: d_u is NULL");
     prepare_fields(c);
-    launch_lattice(c->p.storage, c->P.G, 1, c->pop(c->cur), nullptr, c->boxes(),
+    launch_lattice(c->p.storage, c->P.G, 1, 0, c->pop(c->cur), nullptr, c->boxes(),
                    total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), d_rho, d_u, c->stream);
     return check_async(c);
 }
@@ -575,7 +582,7 @@ int lb_diagnostics(lb_ctx* c, double* h_out)
     if (!h_out) return fail(c, LB_ERR_ARG, "h_out is NULL");
     prepare_fields(c);
     const Geom& G = c->P.G;
-    launch_lattice(c->p.storage, G, 2, c->pop(c->cur), nullptr, c->boxes(), total_points(c) > 0 ? c->toff() : nullptr,
+    launch_lattice(c->p.storage, G, 2, 0, c->pop(c->cur), nullptr, c->boxes(), total_points(c) > 0 ? c->toff() : nullptr,
                    c->tlist(), c->rec(), c->diag(), nullptr, c->stream);
     launch_diag_reduce(G, c->diag(), c->diagout(), c->stream);
     int r = check_async(c);

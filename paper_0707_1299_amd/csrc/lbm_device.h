@@ -48,7 +48,7 @@ struct alignas(16) BoxDev {
     float s_in;        // FP16: dequantise multiplier 2^-e of the stored data
     float s_out;       // FP16: quantise multiplier 2^e of the data written this step
     int e_data;        // FP16: exponent of the data currently stored
-    unsigned maxbits;  // FP16: max |bracket| of the last step (float bits)
+    unsigned spare;
     int nonfinite;     // sticky: non-finite value or FP16 overflow seen
     int pad;
 };

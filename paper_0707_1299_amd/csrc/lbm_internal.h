@@ -25,8 +25,8 @@ struct AdvectLaunch {
 };
 
 bool tile_supported(int tx, int ty, int tz);
-bool launch_lattice(int storage, const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
-                    const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s);
+bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
+                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s);
 void launch_equilibrium(int storage, const Geom& G, void* dst, const BoxDev* boxes, const double* rho,
                         const double* u, hipStream_t s);
 
@@ -36,8 +36,9 @@ void launch_prep(int storage, const Geom& G, long long n, long long off, const d
 long long scan_blocks(long long ntiles);
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
                  int* cursor, int* tlist, int* pslot, hipStream_t s);
-void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist, double* part,
-                       unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s);
+void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
+                       const float* tmax, double* part, float* pmax, unsigned* ticket, BoxDev* boxes, int zero_net,
+                       int fp16_exp, hipStream_t s);
 int box_chunks();
 void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, const int* pslot, const double* partial,
                    hipStream_t s);

@@ -27,11 +27,21 @@ enum Mode { M_STEP = 0, M_MOMENTS = 1, M_DIAG = 2 };
 
 constexpr int CHUNK = 32;  // points reduced per LDS round in the interpolation
 
-template <class S> __device__ __forceinline__ S ld(const S* p) { return __builtin_nontemporal_load(p); }
+template <bool NT, class S> __device__ __forceinline__ S ld(const S* p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
 
 template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_nontemporal_store(v, p); }
 
-template <int ST, int TX, int TY, int TZ, int MODE>
+// VAR bit 0: x-shifted pulls load the lane's own (aligned) element and take
+// the neighbour's from the adjacent lane; only the lanes whose neighbour lies
+// outside the wave (or across the periodic seam) load it directly.
+// VAR bit 1: cached instead of non-temporal population loads.
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR>
 __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
                                                    BoxDev* __restrict__ boxes, const int* __restrict__ toff,
@@ -64,15 +74,29 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
     const S* sb = src + (long long)box * G.sbox;
 
     // ---- pull: population i at x comes from x - c_i
+    constexpr bool SHUF = (VAR & 1) && (TX % 64 == 0);
+    constexpr bool NTL = !(VAR & 2);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T f[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
+        const int cx = cvel(i, 0);
+        const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
         const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
         const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
-        const S v = ld(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
+        const S* row = sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx;
+        T v;
+        if (!SHUF || cx == 0) {
+            v = T(ld<NTL>(row + sx));
+        } else {
+            const T al = T(ld<NTL>(row + x));
+            T sh = cx > 0 ? __shfl_up(al, 1, 64) : __shfl_down(al, 1, 64);
+            const bool direct = cx > 0 ? (lane == 0 || x == 0) : (lane == 63 || x == G.nx - 1);
+            if (direct) sh = T(row[sx]);
+            v = sh;
+        }
         if constexpr (ST == ST_FP16)
-            f[i] = float(v) * float(wgt(i));
+            f[i] = v * float(wgt(i));
         else
             f[i] = v;
     }
@@ -116,7 +140,6 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
     const T rho = T(G.rho0) + drho;
     const T ir = T(1) / rho;
     const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     if constexpr (MODE == M_MOMENTS) {
         if (valid) {
@@ -220,10 +243,8 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
             __shared__ float wm[4];
             if (lane == 0) wm[wave] = m;
             __syncthreads();
-            if (threadIdx.x == 0) {
-                const float mm = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
-                if (mm > 0.0f) atomicMax(&boxes[box].maxbits, __float_as_uint(mm));
-            }
+            // per-tile maximum; the per-box reduction happens before the next step
+            if (threadIdx.x == 0) ((float*)out1)[tile] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
         }
         if (__any(bad) && lane == 0) atomicOr(&boxes[box].nonfinite, 1);
     }
@@ -298,9 +319,20 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
 // ---------------------------------------------------------------------------
 // host-side launchers
 
+template <int ST, int TX, int TY, int TZ, int VAR>
+static void launch_step_v(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
+                          const void* rec, double* out0, double* out1, hipStream_t s)
+{
+    using S = typename StoreT<ST>::S;
+    using T = typename StoreT<ST>::T;
+    hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR>), dim3((unsigned)G.ntiles), dim3(BLOCK), 0, s, G,
+                       (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1);
+}
+
 template <int ST, int TX, int TY, int TZ>
-static void launch_lattice_t(const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
-                             const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+static void launch_lattice_t(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
+                             const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
+                             hipStream_t s)
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
@@ -308,25 +340,33 @@ static void launch_lattice_t(const Geom& G, int mode, const void* src, void* dst
     auto a0 = (const S*)src;
     auto a1 = (S*)dst;
     auto r = (const PRec<T>*)rec;
-    if (mode == M_STEP)
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1, boxes,
-                           toff, tlist, r, out0, out1);
-    else if (mode == M_MOMENTS)
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_MOMENTS>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
+    if (mode == M_STEP) {
+        // bit 0 only changes the code for tiles a whole number of waves wide
+        const int v = TX % 64 == 0 ? (variant & 3) : (variant & 2);
+        switch (v) {
+        case 1: launch_step_v<ST, TX, TY, TZ, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
+        case 2: launch_step_v<ST, TX, TY, TZ, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
+        case 3: launch_step_v<ST, TX, TY, TZ, 3>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
+        default: launch_step_v<ST, TX, TY, TZ, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
+        }
+    } else if (mode == M_MOMENTS) {
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_MOMENTS, 0>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
                            boxes, toff, tlist, r, out0, out1);
-    else
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_DIAG>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1, boxes,
-                           toff, tlist, r, out0, out1);
+    } else {
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_DIAG, 0>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
+                           boxes, toff, tlist, r, out0, out1);
+    }
 }
 
 template <int ST>
-static bool launch_lattice_s(const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
-                             const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+static bool launch_lattice_s(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
+                             const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
+                             hipStream_t s)
 {
-#define LBM_TILE(X, Y, Z)                                                                                  \
-    if (G.tx == X && G.ty == Y && G.tz == Z) {                                                             \
-        launch_lattice_t<ST, X, Y, Z>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);          \
-        return true;                                                                                       \
+#define LBM_TILE(X, Y, Z)                                                                                     \
+    if (G.tx == X && G.ty == Y && G.tz == Z) {                                                                \
+        launch_lattice_t<ST, X, Y, Z>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);    \
+        return true;                                                                                          \
     }
     LBM_TILE(64, 2, 2)
     LBM_TILE(64, 4, 1)
@@ -350,13 +390,13 @@ bool tile_supported(int tx, int ty, int tz)
     return false;
 }
 
-bool launch_lattice(int storage, const Geom& G, int mode, const void* src, void* dst, BoxDev* boxes, const int* toff,
-                    const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
+                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
 {
     switch (storage) {
-    case ST_FP64: return launch_lattice_s<ST_FP64>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);
-    case ST_FP32: return launch_lattice_s<ST_FP32>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);
-    case ST_FP16: return launch_lattice_s<ST_FP16>(G, mode, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    case ST_FP64: return launch_lattice_s<ST_FP64>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    case ST_FP32: return launch_lattice_s<ST_FP32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    case ST_FP16: return launch_lattice_s<ST_FP16>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);
     }
     return false;
 }

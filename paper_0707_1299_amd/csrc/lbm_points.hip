@@ -250,70 +250,77 @@ constexpr int BOX_CHUNKS = 64;
 template <class T>
 __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>* __restrict__ rec,
                                                     const int* __restrict__ toff, const int* __restrict__ tlist,
-                                                    double* __restrict__ part, unsigned* __restrict__ ticket,
+                                                    const float* __restrict__ tmax, double* __restrict__ part,
+                                                    float* __restrict__ pmax, unsigned* __restrict__ ticket,
                                                     BoxDev* __restrict__ boxes, int zero_net, int fp16_exp)
 {
     const int b = blockIdx.x, c = blockIdx.y, C = gridDim.y;
-    if (zero_net) {
-        double s[3] = {0.0, 0.0, 0.0};
-        if (toff) {
-            const long long lo = G.tiles_per_box * c / C, hi = G.tiles_per_box * (c + 1) / C;
-            for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-                const long long tt = (long long)b * G.tiles_per_box + t;
-                for (int k = toff[tt]; k < toff[tt + 1]; ++k) {
-                    const PRec<T>& r = rec[tlist[k]];
-                    int hx = r.bx + 1, hy = r.by + 1, hz = r.bz + 1;
-                    if (hx == G.nx) hx = 0;
-                    if (hy == G.ny) hy = 0;
-                    if (hz == G.nz) hz = 0;
-                    const long long home = (((long long)r.box * G.ntz + hz / G.tz) * G.nty + hy / G.ty) * G.ntx + hx / G.tx;
-                    if (home == tt) {
-                        s[0] += double(r.f[0]);
-                        s[1] += double(r.f[1]);
-                        s[2] += double(r.f[2]);
-                    }
+    const long long lo = G.tiles_per_box * c / C, hi = G.tiles_per_box * (c + 1) / C;
+    double s[3] = {0.0, 0.0, 0.0};
+    float m = 0.0f;
+    for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        const long long tt = (long long)b * G.tiles_per_box + t;
+        if (fp16_exp) m = fmaxf(m, tmax[tt]);
+        if (zero_net && toff) {
+            for (int k = toff[tt]; k < toff[tt + 1]; ++k) {
+                const PRec<T>& r = rec[tlist[k]];
+                int hx = r.bx + 1, hy = r.by + 1, hz = r.bz + 1;
+                if (hx == G.nx) hx = 0;
+                if (hy == G.ny) hy = 0;
+                if (hz == G.nz) hz = 0;
+                const long long home =
+                    (((long long)r.box * G.ntz + hz / G.tz) * G.nty + hy / G.ty) * G.ntx + hx / G.tx;
+                if (home == tt) {
+                    s[0] += double(r.f[0]);
+                    s[1] += double(r.f[1]);
+                    s[2] += double(r.f[2]);
                 }
             }
         }
-        __shared__ double red[4][3];
-        __shared__ int last;
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        for (int k = 0; k < 3; ++k) {
-            const double v = wave_sum(s[k]);
-            if (lane == 0) red[wave][k] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int k = 0; k < 3; ++k)
-                part[((long long)b * C + c) * 3 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-            __threadfence();
-            last = (atomicAdd(&ticket[b], 1u) == unsigned(C - 1));
-        }
-        __syncthreads();
-        if (last && threadIdx.x == 0) {
-            __threadfence();
-            double tot[3] = {0.0, 0.0, 0.0};
-            for (int j = 0; j < C; ++j)
-                for (int k = 0; k < 3; ++k) tot[k] += ((volatile double*)part)[((long long)b * C + j) * 3 + k];
-            for (int k = 0; k < 3; ++k) boxes[b].gc[k] = -tot[k] / double(G.N);
-            ticket[b] = 0u;
-        }
     }
-    if (fp16_exp && c == 0 && threadIdx.x == 0) {
-        BoxDev& B = boxes[b];
+    __shared__ double red[4][3];
+    __shared__ float redm[4];
+    __shared__ int last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum(s[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    m = wave_max(m);
+    if (lane == 0) redm[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k)
+            part[((long long)b * C + c) * 3 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+        pmax[(long long)b * C + c] = fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3]));
+        __threadfence();
+        last = (atomicAdd(&ticket[b], 1u) == unsigned(C - 1));
+    }
+    __syncthreads();
+    if (!(last && threadIdx.x == 0)) return;
+    __threadfence();
+    BoxDev& B = boxes[b];
+    if (zero_net) {
+        double tot[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < C; ++j)
+            for (int k = 0; k < 3; ++k) tot[k] += ((volatile double*)part)[((long long)b * C + j) * 3 + k];
+        for (int k = 0; k < 3; ++k) B.gc[k] = -tot[k] / double(G.N);
+    }
+    if (fp16_exp) {
+        float mx = 0.0f;
+        for (int j = 0; j < C; ++j) mx = fmaxf(mx, ((volatile float*)pmax)[(long long)b * C + j]);
         const int e_in = B.e_data;
-        const float m = __uint_as_float(B.maxbits);
         int e_out = e_in;
-        if (m > 0.0f && m < 3.0e38f) {
-            const float v = ldexpf(m, e_in);
-            if (v > 32768.0f || v < 4096.0f) e_out = 13 - ilogbf(m);
+        if (mx > 0.0f && mx < 3.0e38f) {
+            const float v = ldexpf(mx, e_in);
+            if (v > 32768.0f || v < 4096.0f) e_out = 13 - ilogbf(mx);
         }
         e_out = max(-100, min(120, e_out));
         B.s_in = ldexpf(1.0f, -e_in);
         B.s_out = ldexpf(1.0f, e_out);
         B.e_data = e_out;
-        B.maxbits = 0u;
     }
+    ticket[b] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -563,16 +570,17 @@ void launch_bins(int storage, const Geom& G, long long npts, const void* rec, in
     }
 }
 
-void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist, double* part,
-                       unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s)
+void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
+                       const float* tmax, double* part, float* pmax, unsigned* ticket, BoxDev* boxes, int zero_net,
+                       int fp16_exp, hipStream_t s)
 {
-    const dim3 grid(G.nboxes, zero_net ? BOX_CHUNKS : 1);
+    const dim3 grid(G.nboxes, BOX_CHUNKS);
     if (storage == ST_FP64)
-        hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, part,
-                           ticket, boxes, zero_net, fp16_exp);
+        hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, tmax,
+                           part, pmax, ticket, boxes, zero_net, fp16_exp);
     else
-        hipLaunchKernelGGL(k_box_update<float>, grid, dim3(256), 0, s, G, (const PRec<float>*)rec, toff, tlist, part,
-                           ticket, boxes, zero_net, fp16_exp);
+        hipLaunchKernelGGL(k_box_update<float>, grid, dim3(256), 0, s, G, (const PRec<float>*)rec, toff, tlist, tmax,
+                           part, pmax, ticket, boxes, zero_net, fp16_exp);
 }
 
 int box_chunks() { return BOX_CHUNKS; }

@@ -46,7 +46,7 @@ class lb_params(ctypes.Structure):
         ("rho0", ctypes.c_double), ("tau", ctypes.POINTER(ctypes.c_double)),
         ("max_points", ctypes.c_int64),
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
-        ("fp16_exponent", ctypes.c_int32),
+        ("fp16_exponent", ctypes.c_int32), ("variant", ctypes.c_int32),
     ]
 
 
@@ -123,7 +123,7 @@ def _stream_handle():
 
 
 def make_params(shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_force=False, max_points=0,
-                tile=None, fp16_exponent=0):
+                tile=None, fp16_exponent=0, variant=0):
     """lb_params for boxes of shape (nz, ny, nx); tau is a scalar or a per-box sequence."""
     nz, ny, nx = shape
     taus = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, dtype=np.float64), (nboxes,)))
@@ -138,6 +138,7 @@ def make_params(shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_for
     if tile:
         p.tile_x, p.tile_y, p.tile_z = tile
     p.fp16_exponent = fp16_exponent
+    p.variant = variant
     p._taus = taus  # keep alive
     return p
 
@@ -196,13 +197,13 @@ class Lattice:
     """One liblbm context on the current torch device and stream."""
 
     def __init__(self, shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_force=False, max_points=0,
-                 tile=None, fp16_exponent=0, stream=None):
+                 tile=None, fp16_exponent=0, variant=0, stream=None):
         import torch
         self.torch = torch
         self.shape = tuple(shape)
         self.nboxes = nboxes
         self.params = make_params(shape, storage, nboxes, tau, rho0, zero_net_force, max_points, tile,
-                                  fp16_exponent)
+                                  fp16_exponent, variant)
         nbytes = lb_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()

@@ -1,0 +1,104 @@
+"""Autotuner for the fused step kernel: tile shape x access variant.
+
+    python -m paper_0707_1299_amd.tune --shape 128 128 128 --storage fp32 [--nboxes 1] [--out FILE]
+
+For each candidate it builds a context, warms up, times the fused kernel
+with HIP events (lb_kernel_timing) and keeps the fastest.  Results are
+cached per (arch, storage, box shape, box count) in tune_cache.json next to
+this file; ``lookup`` returns the cached choice or None.  Every candidate
+computes identical results (the parity tests check that bit for bit), so the
+choice only affects speed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tune_cache.json")
+ARCH = "gfx950"
+TILES = [(64, 2, 2), (64, 4, 1), (64, 1, 4), (128, 2, 1), (128, 1, 2), (256, 1, 1), (32, 4, 2), (32, 2, 4),
+         (16, 4, 4)]
+VARIANTS = [0, 1, 2, 3]
+
+
+def key(shape, storage, nboxes):
+    nz, ny, nx = shape
+    return "%s/%s/%dx%dx%d/b%d" % (ARCH, storage, nx, ny, nz, nboxes)
+
+
+def lookup(shape, storage, nboxes=1):
+    if not os.path.exists(CACHE):
+        return None
+    d = json.load(open(CACHE)).get(key(shape, storage, nboxes))
+    if not d:
+        return None
+    return tuple(d["tile"]), int(d["variant"])
+
+
+def candidates(shape):
+    nx = shape[2]
+    out = []
+    for t in TILES:
+        if t[0] > 2 * nx:
+            continue
+        for v in VARIANTS:
+            if (v & 1) and t[0] % 64:
+                continue
+            out.append((t, v))
+    return out
+
+
+def measure(shape, storage, nboxes, tile, variant, steps, points):
+    import torch
+    from . import lbm
+    lat = lbm.Lattice(shape, storage, nboxes=nboxes, tau=0.5, max_points=max(1, len(points[0])), tile=tile,
+                      variant=variant)
+    if len(points[0]):
+        lat.add_point_forces(torch.tensor(points[0], device="cuda"), torch.tensor(points[1], device="cuda"),
+                             None if points[2] is None else torch.tensor(points[2], dtype=torch.int32, device="cuda"))
+    lat.step(10)
+    lat.sync()
+    lat.kernel_timing(True)
+    lat.step(steps)
+    ms, n = lat.kernel_time()
+    lat.close()
+    return ms / n
+
+
+def tune(shape, storage, nboxes=1, steps=100, points=None, save=True, verbose=True):
+    import numpy as np
+    points = points or (np.zeros((0, 3)), np.zeros((0, 3)), None)
+    N = shape[0] * shape[1] * shape[2] * nboxes
+    bpn = {"fp64": 304, "fp32": 152, "fp16": 76}[storage]
+    res = []
+    for tile, variant in candidates(shape):
+        ms = measure(shape, storage, nboxes, tile, variant, steps, points)
+        gbs = bpn * N / (ms * 1e-3) / 1e9
+        res.append(dict(tile=list(tile), variant=variant, kernel_ms=ms, GBs=gbs))
+        if verbose:
+            print("tile %-14s variant %d  %.4f ms  %.1f GB/s" % (tile, variant, ms, gbs), flush=True)
+    best = min(res, key=lambda r: r["kernel_ms"])
+    if save:
+        d = json.load(open(CACHE)) if os.path.exists(CACHE) else {}
+        d[key(shape, storage, nboxes)] = dict(tile=best["tile"], variant=best["variant"],
+                                              kernel_ms=best["kernel_ms"], GBs=best["GBs"])
+        with open(CACHE, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+    return best, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--shape", type=int, nargs=3, default=[128, 128, 128], help="nz ny nx")
+    ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--nboxes", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    a = ap.parse_args()
+    best, _ = tune(tuple(a.shape), a.storage, a.nboxes, a.steps)
+    print(json.dumps(best))
+
+
+if __name__ == "__main__":
+    main()

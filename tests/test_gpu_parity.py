@@ -29,11 +29,11 @@ def rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-def run_gpu(shape, storage, tau, sets, steps, zero_net=False, tile=None, nboxes=1, step_chunks=None):
+def run_gpu(shape, storage, tau, sets, steps, zero_net=False, tile=None, nboxes=1, step_chunks=None, variant=0):
     """sets: list of (pos, force, kind, model_kwargs, box).  Returns (lat, u, per-set outputs)."""
     npts = sum(len(s[0]) for s in sets)
     lat = lbm.Lattice(shape, storage, nboxes=nboxes, tau=tau, zero_net_force=zero_net, max_points=max(npts, 1),
-                      tile=tile)
+                      tile=tile, variant=variant)
     outs = []
     for pos, frc, kind, mkw, box in sets:
         p, f = dev(pos), dev(frc)
@@ -77,9 +77,11 @@ def test_stokeslet_32cubed_500_steps(storage):
     assert rel(U, box.sets[0].U) <= TOL[storage] * 10
 
 
-@pytest.mark.parametrize("storage,tile", [("fp64", None), ("fp64", (16, 4, 4)), ("fp32", (32, 2, 4)),
-                                          ("fp64", (64, 1, 4)), ("fp32", (128, 2, 1))])
-def test_ragged_multi_tile_forces_zero_net(storage, tile):
+@pytest.mark.parametrize("storage,tile,variant", [
+    ("fp64", None, 0), ("fp64", (16, 4, 4), 0), ("fp32", (32, 2, 4), 0), ("fp64", (64, 1, 4), 0),
+    ("fp32", (128, 2, 1), 0), ("fp64", (64, 2, 2), 1), ("fp32", (64, 2, 2), 3), ("fp32", (128, 1, 2), 1),
+    ("fp64", (256, 1, 1), 3), ("fp32", (64, 4, 1), 2), ("fp32", (32, 4, 2), 3)])
+def test_ragged_multi_tile_forces_zero_net(storage, tile, variant):
     """Non-cubic box with ragged tiles on every axis, forces near the periodic seams."""
     shape = (13, 10, 70)
     g = np.random.default_rng(7)
@@ -88,10 +90,10 @@ def test_ragged_multi_tile_forces_zero_net(storage, tile):
     pos[1] = [0.01, 9.99, 0.5]
     frc = g.normal(scale=1e-5, size=(6, 3))
     sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
-    lat, u, outs = run_gpu(shape, storage, 0.8, sets, 60, zero_net=True, tile=tile)
+    lat, u, outs = run_gpu(shape, storage, 0.8, sets, 60, zero_net=True, tile=tile, variant=variant)
     box, uo = run_oracle(shape, 0.8, sets, 60, zero_net=True)
     e = rel(u[0], uo)
-    print("ragged %s %s rel err %.3e" % (storage, tile, e))
+    print("ragged %s %s v%d rel err %.3e" % (storage, tile, variant, e))
     assert e <= TOL[storage]
     assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
 
@@ -211,6 +213,24 @@ def test_batched_boxes_equal_single_runs_bitwise():
                 assert rel(ub[b], uo) <= 1e-10
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
+def test_kernel_variants_bitwise_equal(storage):
+    """The access variants move the same values: identical results bit for bit."""
+    L = 128
+    w = workloads.singularities(L=L, n=16)
+    pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    ref = None
+    for tile, variant in (((64, 2, 2), 0), ((64, 2, 2), 1), ((64, 2, 2), 2), ((64, 2, 2), 3), ((128, 2, 1), 1)):
+        _, u, o = run_gpu((L, L, L), storage, 0.5, sets, 12, tile=tile, variant=variant)
+        if ref is None:
+            ref = (u, o[0][1].cpu().numpy())
+        else:
+            assert np.array_equal(u, ref[0])
+            if tile == (64, 2, 2):     # interpolation partials are summed per tile: same tiling, same bits
+                assert np.array_equal(o[0][1].cpu().numpy(), ref[1])
+
+
 def test_graph_replay_equals_eager_and_is_deterministic():
     pos, frc = workloads.colloids(32, 20)
     frc[:, 2] = -1e-5
@@ -274,3 +294,71 @@ def test_full_size_128_fp32_bench_configuration():
     print("128^3 fp32 rel err %.3e" % e)
     assert e <= TOL["fp32"]
     assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= 1e-4
+
+
+# ---- FP16-scaled storage: error against the FP64 oracle, stated per output ----
+# Storage keeps (fbar_i - w_i rho0)/w_i * 2^e in IEEE half (11-bit significand,
+# round to nearest even) with a per-box power-of-two exponent chosen so the
+# largest stored value sits in [2^12, 2^15).  A single rounding is at most
+# 2^-11 relative to the largest stored value; the velocity is a 19-term
+# moment of such values, re-rounded every step and relaxed by viscosity, so
+# its error against FP64 grows to a few 1e-3 of max|u| over hundreds of steps.
+FP16_BOUND = {"u": 5e-3, "U": 5e-3, "pos": 5e-3}
+
+
+def test_fp16_stokeslet_error_bound():
+    pos, frc = workloads.stokeslet_box(32)
+    sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
+    _, u16, o16 = run_gpu((32, 32, 32), "fp16", 0.5, sets, 500)
+    box, uo = run_oracle((32, 32, 32), 0.5, sets, 500)
+    e = rel(u16[0], uo)
+    eU = rel(o16[0][1].cpu().numpy(), box.sets[0].U)
+    print("fp16 stokeslet: u rel %.3e, U rel %.3e" % (e, eU))
+    assert e <= FP16_BOUND["u"]
+    assert eU <= FP16_BOUND["U"]
+
+
+def test_fp16_colloids_error_bound():
+    shape = (32, 32, 32)
+    pos, frc = workloads.colloids(32, 40)
+    frc[:, 2] = -1e-5
+    model = dict(inv_a=1 / 0.117, inv_aL=0.77)
+    sets = [(pos, frc, lbm.LB_COLLOIDS, model, None)]
+    _, u16, o16 = run_gpu(shape, "fp16", 0.5, sets, 300, zero_net=True)
+    box, uo = run_oracle(shape, 0.5, sets, 300, zero_net=True)
+    e = rel(u16[0], uo)
+    eU = rel(o16[0][1].cpu().numpy(), box.sets[0].U)
+    R = o16[0][0].cpu().numpy()
+    d = np.abs(R - box.sets[0].pos)
+    d = np.minimum(d, 32 - d)
+    disp = np.abs(box.sets[0].pos - pos)
+    disp = np.minimum(disp, 32 - disp).max()
+    print("fp16 colloids: u rel %.3e, U rel %.3e, pos err/disp %.3e" % (e, eU, d.max() / disp))
+    assert e <= FP16_BOUND["u"]
+    assert eU <= FP16_BOUND["U"]
+    assert d.max() <= FP16_BOUND["pos"] * disp
+
+
+def test_fp16_exponent_adapts_and_stays_finite():
+    """Forces doubling every 10 steps (1024x overall): the exponent follows, nothing overflows."""
+    shape = (16, 16, 16)
+    lat = lbm.Lattice(shape, "fp16", tau=0.8, max_points=1)
+    P = np.array([[7.3, 8.1, 6.6]])
+    p = dev(P)
+    box = oracle.Box(shape, 0.8)
+    for k in range(11):
+        F = np.array([[0.0, 0.0, 1e-8 * 2.0 ** k]])
+        lat.clear_forces()
+        f = dev(F)
+        lat.add_point_forces(p, f)
+        lat.step(10)
+        box.sets = [oracle.ForceSet(P, F)]
+        box.step(10)
+    lat.sync()
+    r, d = lat.diagnostics()
+    assert r == lbm.LB_OK and d[0, 11] == 0
+    _, uo = box.moments()
+    _, ug = lat.moments(rho=False)
+    e = rel(ug.cpu().numpy()[0], uo)
+    print("fp16 adaptive exponent: u rel %.3e" % e)
+    assert e <= FP16_BOUND["u"]
