@@ -83,8 +83,8 @@ typedef struct lb_params {
     int32_t tile_z;
     int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default */
     int32_t variant;        /* step-kernel variant bits (same results, different memory access):
-                               1 = x-shifted pulls as aligned loads exchanged between lanes
-                                   (needs tile_x a multiple of 64),
+                               1 = 64-bit per-lane addresses instead of scalar plane bases
+                                   plus 32-bit lane offsets,
                                2 = cached instead of non-temporal population loads */
 } lb_params;
 

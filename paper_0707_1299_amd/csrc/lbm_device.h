@@ -116,6 +116,43 @@ __device__ __forceinline__ void peskin4(double f, double (&w)[4])
     w[3] = (1.0 + 2.0 * f - q) * 0.125;
 }
 
+// Raw buffer access: a wave-uniform descriptor per population plane (scalar
+// registers) and a 32-bit byte offset per lane.  The descriptor's record count
+// is the plane size, so an offset past the plane reads 0 / drops the store
+// instead of touching other memory.  Dword 3 is the gfx9-family value; aux
+// bit 1 marks the access non-temporal.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t plane_rsrc(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class S, int AUX>
+__device__ __forceinline__ S bload(rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(S) == 8)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+    else if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+    else
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+}
+
+template <class S, int AUX>
+__device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(S) == 8)
+    {
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+    }
+    else if constexpr (sizeof(S) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, AUX);
+}
+
 // Wrap r into [0, L).
 __device__ __forceinline__ double wrap_pos(double r, double L)
 {

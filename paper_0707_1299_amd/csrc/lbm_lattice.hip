@@ -37,9 +37,8 @@ template <bool NT, class S> __device__ __forceinline__ S ld(const S* p)
 
 template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_nontemporal_store(v, p); }
 
-// VAR bit 0: x-shifted pulls load the lane's own (aligned) element and take
-// the neighbour's from the adjacent lane; only the lanes whose neighbour lies
-// outside the wave (or across the periodic seam) load it directly.
+// VAR bit 0: global loads/stores with 64-bit per-lane addresses instead of
+// raw buffer accesses (scalar plane descriptor + 32-bit lane offset).
 // VAR bit 1: cached instead of non-temporal population loads.
 template <int ST, int TX, int TY, int TZ, int MODE, int VAR>
 __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
@@ -74,8 +73,11 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
     const S* sb = src + (long long)box * G.sbox;
 
     // ---- pull: population i at x comes from x - c_i
-    constexpr bool SHUF = (VAR & 1) && (TX % 64 == 0);
+    // Each population plane is addressed as a wave-uniform buffer descriptor
+    // plus a 32-bit per-lane byte offset (a plane holds < 4 GiB).
+    constexpr bool WIDE = (VAR & 1);
     constexpr bool NTL = !(VAR & 2);
+    const unsigned pbytes = unsigned(G.sp * (long long)sizeof(S));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T f[NQ];
 #pragma unroll
@@ -84,19 +86,15 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
         const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
         const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
         const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
-        const S* row = sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx;
-        T v;
-        if (!SHUF || cx == 0) {
-            v = T(ld<NTL>(row + sx));
+        S v;
+        if constexpr (WIDE) {
+            v = ld<NTL>(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
         } else {
-            const T al = T(ld<NTL>(row + x));
-            T sh = cx > 0 ? __shfl_up(al, 1, 64) : __shfl_down(al, 1, 64);
-            const bool direct = cx > 0 ? (lane == 0 || x == 0) : (lane == 63 || x == G.nx - 1);
-            if (direct) sh = T(row[sx]);
-            v = sh;
+            const unsigned off = (unsigned(sz) * unsigned(G.ny) + unsigned(sy)) * unsigned(G.nx) + unsigned(sx);
+            v = bload<S, NTL ? 2 : 0>(plane_rsrc(sb + (long long)i * G.sp, pbytes), off * unsigned(sizeof(S)));
         }
         if constexpr (ST == ST_FP16)
-            f[i] = v * float(wgt(i));
+            f[i] = float(v) * float(wgt(i));
         else
             f[i] = v;
     }
@@ -218,14 +216,19 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
 
     // ---- store the post-collision populations at this node
     S* db = dst + (long long)box * G.sbox;
-    const long long n = ((long long)z * G.ny + y) * G.nx + x;
+    const unsigned n = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
     if (valid) {
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
+            S v;
             if constexpr (ST == ST_FP16)
-                st(db + i * G.sp + n, S(br[i] * B.s_out));
+                v = S(br[i] * B.s_out);
             else
-                st(db + i * G.sp + n, S(T(wgt(i)) * br[i]));
+                v = S(T(wgt(i)) * br[i]);
+            if constexpr (WIDE)
+                st(db + i * G.sp + (long long)n, v);
+            else
+                bstore<S, 2>(v, plane_rsrc(db + (long long)i * G.sp, pbytes), n * unsigned(sizeof(S)));
         }
     }
 
@@ -341,9 +344,7 @@ static void launch_lattice_t(const Geom& G, int mode, int variant, const void* s
     auto a1 = (S*)dst;
     auto r = (const PRec<T>*)rec;
     if (mode == M_STEP) {
-        // bit 0 only changes the code for tiles a whole number of waves wide
-        const int v = TX % 64 == 0 ? (variant & 3) : (variant & 2);
-        switch (v) {
+        switch (variant & 3) {
         case 1: launch_step_v<ST, TX, TY, TZ, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
         case 2: launch_step_v<ST, TX, TY, TZ, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
         case 3: launch_step_v<ST, TX, TY, TZ, 3>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;

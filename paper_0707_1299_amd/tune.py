@@ -44,8 +44,6 @@ def candidates(shape):
         if t[0] > 2 * nx:
             continue
         for v in VARIANTS:
-            if (v & 1) and t[0] % 64:
-                continue
             out.append((t, v))
     return out
 
