@@ -27,6 +27,8 @@ BYTES_PER_NODE = {"fp64": 304, "fp32": 152, "fp16": 76}   # 2 x 19 populations x
 WORKLOADS = {
     # name: (shape, storage, tau, kind, n)
     "singularities128": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
+    "boxes512x32_fp32": ((32, 32, 32), "fp32", None, "boxes", 512),
+    "boxes512x32_fp16": ((32, 32, 32), "fp16", None, "boxes", 512),
     "colloids256_fp32": ((256, 256, 256), "fp32", 0.5, "colloids", 10000),
     "colloids256_fp16": ((256, 256, 256), "fp16", 0.5, "colloids", 10000),
     "colloids256_fp64": ((256, 256, 256), "fp64", 0.5, "colloids", 10000),
@@ -38,6 +40,8 @@ DESCR = {
                      "singularities (Stokeslet/stresslet/rotlet, |s|<=1e-5) as %d point forces",
     "colloids": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=1/2, %d sedimenting point colloids "
                 "(F=-1e-6 z, a=0.117), spread + interpolate + advect every step, counter-force on",
+    "boxes": "%d independent %d^3 boxes in one context, %s storage, tau_b ~ U[0.6,1.5], 1-8 fixed colloids "
+             "per box (%d total), counter-force on, interpolated velocity accumulated every step",
 }
 
 
@@ -52,6 +56,9 @@ def make_inputs(kind, shape, n):
     import numpy as np
     from paper_0707_1299_amd import lbm, workloads
     L = shape[0]
+    if kind == "boxes":
+        w = workloads.mobility_boxes(nboxes=n, L=L)
+        return w, None, "boxes", None
     if kind == "singularities":
         w = workloads.singularities(L=L, n=n)
         pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
@@ -60,21 +67,41 @@ def make_inputs(kind, shape, n):
     return pos, frc, "colloid", dict(inv_a=1 / 0.117, inv_aL=0.77)
 
 
-def tuned(shape, storage):
+def tuned(shape, storage, nboxes=1):
     from paper_0707_1299_amd import tune
-    return tune.lookup(shape, storage) or (None, 0)
+    return tune.lookup(shape, storage, nboxes) or (None, 0)
 
 
 def build_lattice(shape, storage, tau, kind, pos, frc, model):
     import torch
     from paper_0707_1299_amd import lbm
+    if kind == "boxes":
+        w = pos
+        nb = len(w["taus"])
+        tile, variant = tuned(shape, storage, nb)
+        lat = lbm.Lattice(shape, storage, nboxes=nb, tau=w["taus"], zero_net_force=True, max_points=len(w["pos"]),
+                          tile=tile, variant=variant)
+        p = torch.tensor(w["pos"], dtype=torch.float64, device="cuda")
+        vsum = torch.zeros_like(p)
+        lat.add_point_forces(p, torch.tensor(w["force"], dtype=torch.float64, device="cuda"),
+                             torch.tensor(w["box"], dtype=torch.int32, device="cuda"), lbm.LB_FORCES_STATIC,
+                             lbm.PointModel(vel_sum=vsum))
+        return lat, p
     tile, variant = tuned(shape, storage)
     lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "colloid"), max_points=len(pos), tile=tile,
                       variant=variant)
     p = torch.tensor(pos, dtype=torch.float64, device="cuda")
     f = torch.tensor(frc, dtype=torch.float64, device="cuda")
     if kind == "colloid":
-        lat.add_point_forces(p, f, None, lbm.LB_COLLOIDS, lbm.PointModel(**model))
+        pm = lbm.PointModel(**{k: v for k, v in model.items() if k != "mlp_seed"})
+        if model.get("mlp_seed") is not None:
+            # network of the learned correction (random weights: same cost as trained ones)
+            from paper_0707_1299_amd import mobility
+            master = torch.tensor(mobility.init_master(model["mlp_seed"]), device="cuda")
+            w16 = torch.zeros(lbm.LBML_NPARAM, dtype=torch.int16, device="cuda")
+            lbm.lbml_round_bf16(master, w16)
+            pm.mlp, pm.in_shift, pm.in_scale, pm.out_scale = w16, mobility.IN_SHIFT, mobility.IN_SCALE, 1e-3
+        lat.add_point_forces(p, f, None, lbm.LB_COLLOIDS, pm)
     else:
         lat.add_point_forces(p, f, None, lbm.LB_FORCES_STATIC)
     return lat, p
@@ -115,6 +142,55 @@ def cpu_baseline(kind, shape, storage, tau, pos, frc, model, budget_s=12.0):
                                        % (steps + 1, steps, dt))
 
 
+def run_workload(name, steps, warmup, timing_steps, mlp=False):
+    """Time one workload; returns (result dict, inputs) for the JSON line."""
+    import torch
+    shape, storage, tau, kind, n = WORKLOADS[name]
+    nb = n if kind == "boxes" else 1
+    N = shape[0] * shape[1] * shape[2] * nb
+    pos, frc, fkind, model = make_inputs(kind, shape, n)
+    if mlp and model is not None:
+        model = dict(model, mlp_seed=0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model)
+        lat.step(warmup)
+        lat.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.sync()
+        elapsed = t1 - t0
+        # dominant kernel: HIP events around every fused-step launch on this stream
+        lat.kernel_timing(True)
+        lat.step(timing_steps)
+        ktot_ms, nlaunch = lat.kernel_time()
+        lat.kernel_timing(False)
+        lat.close()
+    kavg_s = ktot_ms / nlaunch / 1e3
+    achieved = BYTES_PER_NODE[storage] * N / kavg_s / 1e9
+    npts = len(pos["pos"]) if kind == "boxes" else len(pos)
+    r = dict(mlups=N * steps / elapsed / 1e6, ms_per_step=elapsed / steps * 1e3, kernel_ms=kavg_s * 1e3,
+             achieved_GBs=achieved, frac=achieved / PEAK_HBM_GBS, nodes=N, points=int(npts), storage=storage,
+             launches_timed=nlaunch, steps=steps)
+    if kind in ("colloid", "colloids"):
+        r["colloid_updates_per_s"] = n * steps / elapsed
+    if kind == "boxes":
+        r["point_updates_per_s"] = npts * steps / elapsed
+    return r, (shape, storage, tau, kind, n, pos, frc, fkind, model)
+
+
+def describe(name, r):
+    shape, storage, tau, kind, n = WORKLOADS[name]
+    if kind == "singularities":
+        return DESCR[kind] % (shape[0], storage, n, r["points"])
+    if kind == "boxes":
+        return DESCR[kind] % (n, shape[0], storage, r["points"])
+    return DESCR[kind] % (shape[0], storage, n)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +199,7 @@ def main():
     ap.add_argument("--workload", default="singularities128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=500)
+    ap.add_argument("--all", action="store_true", help="also time the other workloads (reported under 'workloads')")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this build "
@@ -133,72 +210,61 @@ def main():
     import torch
     from paper_0707_1299_amd import lbm  # noqa: F401  (fails loudly if the library is missing)
 
-    shape, storage, tau, kind, n = WORKLOADS[a.workload]
-    N = shape[0] * shape[1] * shape[2]
-    pos, frc, fkind, model = make_inputs(kind, shape, n)
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model)
-        lat.step(a.warmup)
-        lat.sync()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lat.step(a.steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        lat.sync()
-        elapsed = t1 - t0
-        ms_per_step = elapsed / a.steps * 1e3
-        mlups = N * a.steps / elapsed / 1e6
-
-        # dominant kernel: HIP events around every fused-step launch on this stream
-        lat.kernel_timing(True)
-        lat.step(a.timing_steps)
-        ktot_ms, nlaunch = lat.kernel_time()
-        lat.kernel_timing(False)
-        kavg_s = ktot_ms / nlaunch / 1e3
-        alg_bytes = BYTES_PER_NODE[storage] * N
-        achieved = alg_bytes / kavg_s / 1e9
-        traffic = traffic_from_profile(a.workload, storage, N)
-
+    r, inp = run_workload(a.workload, a.steps, a.warmup, a.timing_steps)
+    shape, storage, tau, kind, n, pos, frc, fkind, model = inp
+    traffic = traffic_from_profile(a.workload, storage, r["nodes"])
+    tile, variant = tuned(shape, storage)
     out = {
         "metric": "MLUPS and % HBM roofline; colloid updates/s vs plain FP32 at stated error",
-        "value": round(mlups, 1),
+        "value": round(r["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(r["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32"}[storage],
         "data": "synthetic",
-        "config": {"workload": DESCR[kind] % ((shape[0], storage, n) + ((len(pos),) if kind == "singularities" else ())),
-                   "nodes": N, "points": int(len(pos)), "seed": 20261200 + (2 if kind == "singularities" else 3),
-                   "tile": list(tuned(shape, storage)[0] or ()), "variant": tuned(shape, storage)[1]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+        "config": {"workload": describe(a.workload, r), "nodes": r["nodes"], "points": r["points"],
+                   "seed": 20261200 + {"singularities": 2, "colloids": 3, "boxes": 4}[kind],
+                   "tile": list(tile or ()), "variant": variant},
+        "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(r["frac"], 4), "traffic": traffic,
                      "kernel": "k_lattice step (fused spread/pull/collide/store/interpolate)",
-                     "bytes_per_node": BYTES_PER_NODE[storage], "kernel_ms": round(kavg_s * 1e3, 5),
-                     "launches_timed": nlaunch},
+                     "bytes_per_node": BYTES_PER_NODE[storage], "kernel_ms": round(r["kernel_ms"], 5),
+                     "launches_timed": r["launches_timed"]},
     }
-    if kind == "colloid":
-        out["colloid_updates_per_s"] = round(n * a.steps / elapsed, 1)
+    if "colloid_updates_per_s" in r:
+        out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)
 
-    if not a.no_cpu:
+    if not a.no_cpu and kind != "boxes":
         box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
         out["cpu_baseline"] = cb
         # same number of steps on a fresh GPU lattice: error of this storage against the oracle
+        stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            pos2, frc2, _, _ = make_inputs(kind, shape, n)
-            lat2, _ = build_lattice(shape, storage, tau, fkind, pos2, frc2, model)
+            lat2, _ = build_lattice(shape, storage, tau, fkind, pos, frc, model)
             lat2.step(csteps)
             _, u = lat2.moments(rho=False)
             lat2.sync()
         _, uo = box.moments()
         err = float(np.abs(u.cpu().numpy()[0] - uo).max() / np.abs(uo).max())
         out["error_vs_oracle"] = {"velocity_rel_linf": err, "steps": csteps}
+
+    if a.all:
+        extra = {}
+        for name, steps, mlp in (("colloids256_fp32", 300, False), ("colloids256_fp16", 300, False),
+                                 ("colloids256_fp64", 200, False), ("colloids512_fp32", 100, False),
+                                 ("colloids512_fp16", 100, False), ("colloids512_fp16", 100, True),
+                                 ("boxes512x32_fp32", 300, False), ("boxes512x32_fp16", 300, False)):
+            rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
+            rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
+            extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                                     for k, v in rr.items()}
+            print("workload %s done" % name, file=sys.stderr, flush=True)
+        out["workloads"] = extra
     print(json.dumps(out))
 
 

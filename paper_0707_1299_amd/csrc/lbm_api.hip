@@ -104,8 +104,13 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.maxp = max_axis_tiles(p->nx, tx) * max_axis_tiles(p->ny, ty) * max_axis_tiles(p->nz, tz);
     if (G.ntiles >= (1LL << 31) - 1) { why = "too many tiles"; return LB_ERR_SIZE; }
     P.cap = p->max_points;
-    if (P.cap * G.maxp >= (1LL << 31) - 1) { why = "max_points too large"; return LB_ERR_SIZE; }
-    P.chunks = box_chunks();
+    if (P.cap * G.maxp >= (1LL << 31) - 1 || P.cap >= (1LL << (31 - PK_BITS))) {
+        why = "max_points too large";
+        return LB_ERR_SIZE;
+    }
+    if (G.maxp > (1 << PK_BITS)) { why = "tile too small for the stencil"; return LB_ERR_ARG; }
+    G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
+    P.chunks = G.bchunks;
     Layout& L = P.L;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
@@ -162,6 +167,7 @@ struct lb_ctx {
     std::vector<Set> sets;
     unsigned long long gen;
     bool bins_valid;
+    bool gc_valid;   // counter-force sums current for the registered static sets
     std::vector<GraphEntry> graphs;
     bool timing;
     std::vector<hipEvent_t> ev;
@@ -193,11 +199,20 @@ struct lb_ctx {
 
 namespace {
 
+thread_local std::string g_err;  // message of the last failure without a context
+
 int fail(lb_ctx* c, int code, const std::string& msg)
 {
-    if (c) c->err = msg;
+    if (c)
+        c->err = msg;
+    else
+        g_err = msg;
     return code;
 }
+
+// Launch errors are read with hipGetLastError after our own launches; drop
+// any error an earlier, unrelated runtime call left behind first.
+void clear_stale_error() { (void)hipGetLastError(); }
 
 int hip_check(lb_ctx* c, hipError_t e, const char* what)
 {
@@ -231,15 +246,20 @@ void build_points(lb_ctx* c, hipStream_t s)
     }
     launch_bins(c->p.storage, G, off, c->rec(), c->count(), c->bsum(), c->toff(), c->cursor(), c->tlist(),
                 c->pslot(), s);
+    c->gc_valid = false;
 }
 
+// per-box work before a step or a read: the counter-force sums (only when the
+// point records may have changed since they were last taken) and the FP16
+// exponent of the coming step
 void box_update(lb_ctx* c, hipStream_t s, bool fp16_exp)
 {
-    const bool zero_net = c->p.zero_net_force != 0;
+    const bool sums = c->p.zero_net_force != 0 && !c->gc_valid;
     const bool fp16 = fp16_exp && c->p.storage == LB_STORAGE_FP16;
-    if (!zero_net && !fp16) return;
+    if (!sums && !fp16) return;
     launch_box_update(c->p.storage, c->P.G, c->rec(), total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->tmax(),
-                      c->fpart(), c->pmax(), c->ticket(), c->boxes(), zero_net ? 1 : 0, fp16 ? 1 : 0, s);
+                      c->fpart(), c->pmax(), c->ticket(), c->boxes(), sums ? 1 : 0, fp16 ? 1 : 0, s);
+    if (sums) c->gc_valid = true;
 }
 
 // one step on stream s; flips c->cur
@@ -352,28 +372,30 @@ extern "C" {
 
 int lb_workspace_bytes(const lb_params* p, size_t* bytes)
 {
-    if (!bytes) return LB_ERR_ARG;
+    if (!bytes) return fail(nullptr, LB_ERR_ARG, "bytes is NULL");
     Plan P;
     std::string why;
     const int r = make_plan(p, P, why);
-    if (r) return r;
+    if (r) return fail(nullptr, r, why);
     *bytes = P.L.total;
     return LB_OK;
 }
 
 int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_stream, lb_ctx** out)
 {
-    if (!out) return LB_ERR_ARG;
+    if (!out) return fail(nullptr, LB_ERR_ARG, "out is NULL");
     *out = nullptr;
+    clear_stale_error();
     Plan P;
     std::string why;
     int r = make_plan(p, P, why);
-    if (r) return r;
-    if (!p->tau) return LB_ERR_ARG;
+    if (r) return fail(nullptr, r, why);
+    if (!p->tau) return fail(nullptr, LB_ERR_ARG, "tau is NULL");
     for (int b = 0; b < p->nboxes; ++b)
-        if (!(p->tau[b] > 0.0) || !isfinite(p->tau[b])) return LB_ERR_ARG;
-    if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return LB_ERR_ARG;
-    if (bytes < P.L.total) return LB_ERR_SIZE;
+        if (!(p->tau[b] > 0.0) || !isfinite(p->tau[b])) return fail(nullptr, LB_ERR_ARG, "tau must be finite and > 0");
+    if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0)
+        return fail(nullptr, LB_ERR_ARG, "workspace NULL or not 256-byte aligned");
+    if (bytes < P.L.total) return fail(nullptr, LB_ERR_SIZE, "workspace too small");
     lb_ctx* c = new lb_ctx();
     c->p = *p;
     c->tau.assign(p->tau, p->tau + p->nboxes);
@@ -385,6 +407,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->cur = 0;
     c->gen = 1;
     c->bins_valid = false;
+    c->gc_valid = false;
     c->timing = false;
     c->ev_used = 0;
     c->timed_ms = 0.0;
@@ -416,6 +439,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
                   "hipMemcpyAsync");
     if (!r) r = check_async(c);
     if (r) {
+        g_err = c->err;
         delete c;
         return r;
     }
@@ -433,6 +457,7 @@ int lb_set_stream(lb_ctx* c, void* hip_stream)
 int lb_set_equilibrium(lb_ctx* c, const double* d_rho, const double* d_u)
 {
     if (!c) return LB_ERR_ARG;
+    clear_stale_error();
     if (!d_rho || !d_u) return fail(c, LB_ERR_ARG, "lb_set_equilibrium: NULL field");
     launch_equilibrium(c->p.storage, c->P.G, c->pop(c->cur), c->boxes(), d_rho, d_u, c->stream);
     return check_async(c);
@@ -468,6 +493,7 @@ int lb_add_point_forces(lb_ctx* c, int64_t n, const double* d_pos, const double*
     c->sets.push_back(s);
     c->gen++;
     c->bins_valid = false;
+    c->gc_valid = false;
     return LB_OK;
 }
 
@@ -477,12 +503,14 @@ int lb_clear_forces(lb_ctx* c)
     c->sets.clear();
     c->gen++;
     c->bins_valid = false;
+    c->gc_valid = false;
     return LB_OK;
 }
 
 int lb_step(lb_ctx* c, int32_t nsteps)
 {
     if (!c) return LB_ERR_ARG;
+    clear_stale_error();
     if (nsteps < 0) return fail(c, LB_ERR_ARG, "nsteps < 0");
     if (nsteps == 0) return LB_OK;
     int left = nsteps;
@@ -493,6 +521,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
                       c->sets.end());
         c->gen++;
         c->bins_valid = false;
+        c->gc_valid = false;
         c->steps++;
         left--;
     }
@@ -502,6 +531,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
         build_points(c, c->stream);
         c->bins_valid = true;
     }
+    if (left > 0 && !moving) box_update(c, c->stream, false);   // static sums outside any captured graph
     const bool rebuild = moving;
     if (c->timing || left < 4) {
         for (int k = 0; k < left; ++k) enqueue_step(c, c->stream, rebuild);
@@ -532,6 +562,7 @@ static int prepare_fields(lb_ctx* c)
 int lb_moments(lb_ctx* c, double* d_rho, double* d_u)
 {
     if (!c) return LB_ERR_ARG;
+    clear_stale_error();
     if (!d_u) return fail(c, LB_ERR_ARG, "lb_moments: d_u is NULL");
     prepare_fields(c);
     launch_lattice(c->p.storage, c->P.G, 1, 0, c->pop(c->cur), nullptr, c->boxes(),
@@ -542,6 +573,7 @@ int lb_moments(lb_ctx* c, double* d_rho, double* d_u)
 int lb_interp_velocity(lb_ctx* c, int64_t n, const double* d_pos, const int32_t* d_box, double* d_u_out)
 {
     if (!c) return LB_ERR_ARG;
+    clear_stale_error();
     if (n < 0) return fail(c, LB_ERR_ARG, "n < 0");
     if (n == 0) return LB_OK;
     if (!d_pos || !d_u_out) return fail(c, LB_ERR_ARG, "NULL positions or output");
@@ -579,6 +611,7 @@ static int read_flags(lb_ctx* c)
 int lb_diagnostics(lb_ctx* c, double* h_out)
 {
     if (!c) return LB_ERR_ARG;
+    clear_stale_error();
     if (!h_out) return fail(c, LB_ERR_ARG, "h_out is NULL");
     prepare_fields(c);
     const Geom& G = c->P.G;
@@ -628,7 +661,7 @@ const char* lb_status_string(int status)
     return "unknown status";
 }
 
-const char* lb_last_error(const lb_ctx* c) { return c ? c->err.c_str() : "no context"; }
+const char* lb_last_error(const lb_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 int64_t lb_steps_taken(const lb_ctx* c) { return c ? c->steps : -1; }
 

@@ -30,6 +30,12 @@ template <> struct StoreT<ST_FP64> { using S = double; using T = double; };
 template <> struct StoreT<ST_FP32> { using S = float; using T = float; };
 template <> struct StoreT<ST_FP16> { using S = _Float16; using T = float; };
 
+// Entries of the per-tile point lists: point index and the index of this tile
+// among the tiles that point's stencil touches.
+constexpr int PK_BITS = 6;
+__host__ __device__ constexpr int pk_point(int e) { return e >> PK_BITS; }
+__host__ __device__ constexpr int pk_slot(int e) { return e & ((1 << PK_BITS) - 1); }
+
 // Per-point record rebuilt before every step that needs it: base node of the
 // 4-wide stencil (floor(R) - 1, wrapped), the three sets of one-dimensional
 // kernel weights, and the force, in the arithmetic type of the storage mode.
@@ -59,7 +65,7 @@ struct Geom {
     int tx, ty, tz;       // tile extent per axis (tx * ty * tz == BLOCK)
     int ntx, nty, ntz;    // tiles per axis
     int maxp;             // max tiles touched by one point's stencil
-    int pad;
+    int bchunks;          // blocks per box of the per-box force / maximum reductions
     long long N;          // nodes per box
     long long sp;         // elements between population planes
     long long sbox;       // elements between boxes (NQ * sp)
@@ -88,20 +94,63 @@ __device__ __forceinline__ T stencil_w(int x, int base, int n, const T (&w)[4])
     return d == 0 ? w[0] : d == 1 ? w[1] : d == 2 ? w[2] : d == 3 ? w[3] : T(0);
 }
 
+// Cross-lane moves within a wave64 (DPP).  Lanes whose source is outside the
+// pattern, or whose row is masked off, receive 0.
+template <int CTRL, int ROW, int BANK, bool BC>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW, BANK, BC));
+}
+
+template <int CTRL, int ROW, int BANK, bool BC>
+__device__ __forceinline__ double dpp(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW, BANK, BC);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW, BANK, BC);
+    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ float lane63(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+__device__ __forceinline__ double lane63(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, (long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Sum over the 64 lanes (all lanes must be active), returned to every lane.
+// Fixed tree: shifts by 1, 2, 4, 8 within each 16-lane row, then row 0 -> 1
+// and row 2 -> 3 (row_bcast:15), then rows 0-1 -> 2-3 (row_bcast:31); lane 63
+// ends with the total.
 template <class T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp<0x111, 0xf, 0xf, true>(v);
+    v += dpp<0x112, 0xf, 0xf, true>(v);
+    v += dpp<0x114, 0xf, 0xf, true>(v);
+    v += dpp<0x118, 0xf, 0xf, true>(v);
+    v += dpp<0x142, 0xa, 0xf, false>(v);
+    v += dpp<0x143, 0xc, 0xf, false>(v);
+    return lane63(v);
 }
 
+// Maximum over the 64 lanes of non-negative values (masked lanes read 0).
 template <class T>
 __device__ __forceinline__ T wave_max(T v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp<0x111, 0xf, 0xf, true>(v));
+    v = fmax(v, dpp<0x112, 0xf, 0xf, true>(v));
+    v = fmax(v, dpp<0x114, 0xf, 0xf, true>(v));
+    v = fmax(v, dpp<0x118, 0xf, 0xf, true>(v));
+    v = fmax(v, dpp<0x142, 0xa, 0xf, false>(v));
+    v = fmax(v, dpp<0x143, 0xc, 0xf, false>(v));
+    return lane63(v);
 }
 
 // Peskin's 4-point kernel at the four nodes floor(r)-1 .. floor(r)+2 for a

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
         k1 = toff[tile + 1];
     }
     for (int k = k0; k < k1; ++k) {
-        const PRec<T>& r = rec[tlist[k]];
+        const PRec<T>& r = rec[pk_point(tlist[k])];
         const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
                     stencil_w<T>(z, r.bz, G.nz, r.wz);
         gx += r.f[0] * w;
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
         for (int c0 = k0; c0 < k1; c0 += CHUNK) {
             const int cn = min(CHUNK, k1 - c0);
             for (int kk = 0; kk < cn; ++kk) {
-                const PRec<T>& r = rec[tlist[c0 + kk]];
+                const PRec<T>& r = rec[pk_point(tlist[c0 + kk])];
                 T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
                       stencil_w<T>(z, r.bz, G.nz, r.wz);
                 if (!valid) w = T(0);

@@ -190,22 +190,19 @@ __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, cons
             for (int ix = 0; ix < s.cx; ++ix) {
                 const long long t = tile_id(G, r.box, s.tz[iz], s.ty[iy], s.tx[ix]);
                 const int slot = toff[t] + atomicAdd(&cursor[t], 1);
-                tlist[slot] = (int)p;
+                tlist[slot] = int(p << PK_BITS) | ((iz * s.cy + iy) * s.cx + ix);
             }
 }
 
 // 4. sort every tile's list by point index (so sums run in a fixed order) and
 //    record, for each point and each tile it touches, where it sits in that
 //    tile's list.
-template <class T>
-__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const PRec<T>* __restrict__ rec,
-                                                    const int* __restrict__ toff, int* __restrict__ tlist,
+__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const int* __restrict__ toff, int* __restrict__ tlist,
                                                     int* __restrict__ pslot)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= G.ntiles) return;
     const int a = toff[t], b = toff[t + 1];
-    if (a == b) return;
     for (int i = a + 1; i < b; ++i) {
         const int v = tlist[i];
         int j = i - 1;
@@ -215,26 +212,9 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const PRec<T>*
         }
         tlist[j + 1] = v;
     }
-    // this tile's coordinates
-    long long q = t;
-    const int itx = int(q % G.ntx);
-    q /= G.ntx;
-    const int ity = int(q % G.nty);
-    q /= G.nty;
-    const int itz = int(q % G.ntz);
     for (int i = a; i < b; ++i) {
-        const int p = tlist[i];
-        const PRec<T> r = rec[p];
-        TileSet s;
-        point_tiles(G, r.bx, r.by, r.bz, s);
-        int jx = 0, jy = 0, jz = 0;
-        for (int k = 0; k < s.cx; ++k)
-            if (s.tx[k] == itx) jx = k;
-        for (int k = 0; k < s.cy; ++k)
-            if (s.ty[k] == ity) jy = k;
-        for (int k = 0; k < s.cz; ++k)
-            if (s.tz[k] == itz) jz = k;
-        pslot[(long long)p * G.maxp + (jz * s.cy + jy) * s.cx + jx] = i;
+        const int e = tlist[i];
+        pslot[(long long)pk_point(e) * G.maxp + pk_slot(e)] = i;
     }
 }
 
@@ -245,8 +225,6 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const PRec<T>*
 //    once, in its home tile (the tile of node floor(R)), over the box's own
 //    tiles in a fixed chunking, so the result does not depend on how many
 //    boxes share the launch or on the order the bins were filled.
-constexpr int BOX_CHUNKS = 64;
-
 template <class T>
 __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>* __restrict__ rec,
                                                     const int* __restrict__ toff, const int* __restrict__ tlist,
@@ -254,16 +232,17 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
                                                     float* __restrict__ pmax, unsigned* __restrict__ ticket,
                                                     BoxDev* __restrict__ boxes, int zero_net, int fp16_exp)
 {
+    // block (b, c) covers tiles [256 c, 256 c + 256) of box b, one tile per thread
     const int b = blockIdx.x, c = blockIdx.y, C = gridDim.y;
-    const long long lo = G.tiles_per_box * c / C, hi = G.tiles_per_box * (c + 1) / C;
+    const long long t = (long long)c * blockDim.x + threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
     float m = 0.0f;
-    for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    if (t < G.tiles_per_box) {
         const long long tt = (long long)b * G.tiles_per_box + t;
-        if (fp16_exp) m = fmaxf(m, tmax[tt]);
+        if (fp16_exp) m = tmax[tt];
         if (zero_net && toff) {
             for (int k = toff[tt]; k < toff[tt + 1]; ++k) {
-                const PRec<T>& r = rec[tlist[k]];
+                const PRec<T>& r = rec[pk_point(tlist[k])];
                 int hx = r.bx + 1, hy = r.by + 1, hz = r.bz + 1;
                 if (hx == G.nx) hx = 0;
                 if (hy == G.ny) hy = 0;
@@ -297,18 +276,29 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
         last = (atomicAdd(&ticket[b], 1u) == unsigned(C - 1));
     }
     __syncthreads();
-    if (!(last && threadIdx.x == 0)) return;
+    if (!last) return;
+    // the last block of the box combines the C partials in a fixed order
     __threadfence();
-    BoxDev& B = boxes[b];
-    if (zero_net) {
-        double tot[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < C; ++j)
-            for (int k = 0; k < 3; ++k) tot[k] += ((volatile double*)part)[((long long)b * C + j) * 3 + k];
-        for (int k = 0; k < 3; ++k) B.gc[k] = -tot[k] / double(G.N);
+    double tot[3] = {0.0, 0.0, 0.0};
+    float mx = 0.0f;
+    for (int j = threadIdx.x; j < C; j += blockDim.x) {
+        for (int k = 0; k < 3; ++k) tot[k] += ((volatile double*)part)[((long long)b * C + j) * 3 + k];
+        mx = fmaxf(mx, ((volatile float*)pmax)[(long long)b * C + j]);
     }
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum(tot[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    mx = wave_max(mx);
+    if (lane == 0) redm[wave] = mx;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    BoxDev& B = boxes[b];
+    if (zero_net)
+        for (int k = 0; k < 3; ++k) B.gc[k] = -(((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]) / double(G.N);
     if (fp16_exp) {
-        float mx = 0.0f;
-        for (int j = 0; j < C; ++j) mx = fmaxf(mx, ((volatile float*)pmax)[(long long)b * C + j]);
+        mx = fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3]));
         const int e_in = B.e_data;
         int e_out = e_in;
         if (mx > 0.0f && mx < 3.0e38f) {
@@ -478,7 +468,7 @@ __global__ __launch_bounds__(256) void k_interp_points(const Geom G, long long n
     if (toff) {
         const long long t = tile_id(G, box, z / G.tz, y / G.ty, x / G.tx);
         for (int k = toff[t]; k < toff[t + 1]; ++k) {
-            const PRec<T>& r = rec[tlist[k]];
+            const PRec<T>& r = rec[pk_point(tlist[k])];
             const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
                         stencil_w<T>(z, r.bz, G.nz, r.wz);
             gx += r.f[0] * w;
@@ -560,13 +550,13 @@ void launch_bins(int storage, const Geom& G, long long npts, const void* rec, in
     if (storage == ST_FP64) {
         hipLaunchKernelGGL(k_fill<double>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts,
                            (const PRec<double>*)rec, (const int*)toff, cursor, tlist);
-        hipLaunchKernelGGL(k_sort_slots<double>, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G,
-                           (const PRec<double>*)rec, (const int*)toff, tlist, pslot);
+        hipLaunchKernelGGL(k_sort_slots, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G, (const int*)toff, tlist,
+                           pslot);
     } else {
         hipLaunchKernelGGL(k_fill<float>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts, (const PRec<float>*)rec,
                            (const int*)toff, cursor, tlist);
-        hipLaunchKernelGGL(k_sort_slots<float>, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G,
-                           (const PRec<float>*)rec, (const int*)toff, tlist, pslot);
+        hipLaunchKernelGGL(k_sort_slots, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G, (const int*)toff, tlist,
+                           pslot);
     }
 }
 
@@ -574,7 +564,7 @@ void launch_box_update(int storage, const Geom& G, const void* rec, const int* t
                        const float* tmax, double* part, float* pmax, unsigned* ticket, BoxDev* boxes, int zero_net,
                        int fp16_exp, hipStream_t s)
 {
-    const dim3 grid(G.nboxes, BOX_CHUNKS);
+    const dim3 grid(G.nboxes, G.bchunks);
     if (storage == ST_FP64)
         hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, tmax,
                            part, pmax, ticket, boxes, zero_net, fp16_exp);
@@ -583,7 +573,6 @@ void launch_box_update(int storage, const Geom& G, const void* rec, const int* t
                            part, pmax, ticket, boxes, zero_net, fp16_exp);
 }
 
-int box_chunks() { return BOX_CHUNKS; }
 
 void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, const int* pslot, const double* partial,
                    hipStream_t s)

@@ -62,6 +62,10 @@ class lb_point_model(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("liblbm.so is not built (%s); run python -m paper_0707_1299_amd.build" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the library binds to that one instead of a second runtime from
+    # /opt/rocm (two runtimes in one process do not share the device).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     P = ctypes.POINTER
@@ -147,7 +151,7 @@ def lb_workspace_bytes(p: lb_params) -> int:
     n = ctypes.c_size_t(0)
     r = _L.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
     if r != LB_OK:
-        raise LBError(r)
+        raise LBError(r, _L.lb_last_error(None).decode())
     return n.value
 
 
@@ -213,7 +217,7 @@ class Lattice:
         r = _L.lb_init(ctypes.byref(self.params), ctypes.c_void_p(self._ws), nbytes,
                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
         if r != LB_OK:
-            raise LBError(r)
+            raise LBError(r, _L.lb_last_error(None).decode())
         self.ctx = ctx
         self._keep = []   # tensors that must outlive their use by queued work
 
