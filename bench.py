@@ -200,7 +200,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=500)
     ap.add_argument("--all", action="store_true", help="also time the other workloads (reported under 'workloads')")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 10 device copies of 512 MiB (reference for the HBM byte counters)")
     a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": 1 << 29, "copies": 10}))
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this build "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)

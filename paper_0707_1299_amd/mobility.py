@@ -6,10 +6,14 @@ Workflow, all on the GPU through the C ABI:
    context, one fixed colloid per box at a chosen sub-node offset and the
    box's own tau, counter-force on; the interpolated fluid velocity U is
    averaged over the last steps and turned into the dimensionless mobility
-   mu = 6 pi eta U.F / |F|^2 (the quantity 1/a_L of Sec. IV at that offset and
-   box size).
+   mu(L) = 6 pi eta U.F / |F|^2 (1/a_L of Sec. IV at that offset, tau and box
+   size L).  ``self_part`` removes the periodic images to first order,
+   mu_self = mu(L) + k / L with the cubic-array coefficient k = 2.84 of the
+   Fig. 5 law v = v0 / (1 + k a / L); mu_self is what the colloid update
+   needs as 1/a_L so that a colloid in any box keeps the physical periodic
+   slowdown.
 2. ``train``: full-batch Adam on the library's MLP kernels (lbml_*), target
-   (mu - mu_plain) / out_scale, features (2 o - 1, (tau - 1.05) / 0.45).
+   (mu_self - mu_plain) / out_scale, features (2 o - 1, (tau - 1.05) / 0.45).
 3. ``evaluate``: on held-out single-particle runs, the error of the plain
    constant against the error of constant + MLP.
 
@@ -27,6 +31,12 @@ from . import lbm
 
 IN_SHIFT = (0.5, 0.5, 0.5, 1.05)
 IN_SCALE = (2.0, 2.0, 2.0, 1.0 / 0.45)
+PERIODIC_K = 2.84   # v = v0 / (1 + k a / L) for a simple-cubic array (Fig. 5)
+
+
+def self_part(mu, L):
+    """Lattice self-mobility with the periodic images removed to first order."""
+    return np.asarray(mu, dtype=np.float64) + PERIODIC_K / L
 
 
 def features(offsets, taus):
