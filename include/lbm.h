@@ -85,7 +85,9 @@ typedef struct lb_params {
     int32_t variant;        /* step-kernel variant bits (same results, different memory access):
                                1 = 64-bit per-lane addresses instead of scalar plane bases
                                    plus 32-bit lane offsets,
-                               2 = cached instead of non-temporal population loads */
+                               2 = cached instead of non-temporal population loads,
+                               4 * k (k = 0..3) = each block of the step kernel works
+                                   through 2^k consecutive tiles */
 } lb_params;
 
 /*
@@ -199,9 +201,10 @@ int64_t lb_steps_taken(const lb_ctx* ctx);
 
 /*
  * Timing of the fused step kernel: with enable = 1, lb_step launches eagerly
- * and brackets every fused-kernel launch with HIP events on the context's
- * stream; lb_kernel_time waits for the stream and returns the summed
- * duration (ms) and the number of launches since it was enabled.
+ * and every fused-kernel launch carries a pair of HIP events that the runtime
+ * stamps at the kernel's own start and end on the context's stream;
+ * lb_kernel_time waits for the stream and returns the summed duration (ms)
+ * and the number of launches since timing was enabled.
  */
 int lb_kernel_timing(lb_ctx* ctx, int enable);
 int lb_kernel_time(lb_ctx* ctx, double* total_ms, int64_t* launches);

@@ -84,7 +84,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_FP16) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
-    if (p->variant < 0 || p->variant > 3) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if (p->variant < 0 || p->variant > 15) { why = "unknown kernel variant"; return LB_ERR_ARG; }
     int tx, ty, tz;
     choose_tile(p, tx, ty, tz);
     if (!tile_supported(tx, ty, tz)) { why = "unsupported tile shape"; return LB_ERR_ARG; }
@@ -110,6 +110,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     }
     if (G.maxp > (1 << PK_BITS)) { why = "tile too small for the stencil"; return LB_ERR_ARG; }
     G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
+    G.tpb = 1 << ((p->variant >> 2) & 3);
     P.chunks = G.bchunks;
     Layout& L = P.L;
     size_t o = 0;
@@ -280,14 +281,10 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
         }
         e0 = c->ev[c->ev_used++];
         e1 = c->ev[c->ev_used++];
-        (void)hipEventRecord(e0, s);
-    }
-    launch_lattice(c->p.storage, G, 0, c->p.variant, c->pop(c->cur), c->pop(c->cur ^ 1), c->boxes(), npts > 0 ? c->toff() : nullptr,
-                   c->tlist(), c->rec(), c->partial(), (double*)c->tmax(), s);
-    if (c->timing) {
-        (void)hipEventRecord(e1, s);
         c->timed_launches++;
     }
+    launch_lattice(c->p.storage, G, 0, c->p.variant, c->pop(c->cur), c->pop(c->cur ^ 1), c->boxes(),
+                   npts > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), c->partial(), (double*)c->tmax(), s, e0, e1);
     long long off = 0;
     for (auto& st : c->sets) {
         const bool adv = st.kind == LB_COLLOIDS;
@@ -565,7 +562,9 @@ int lb_moments(lb_ctx* c, double* d_rho, double* d_u)
     clear_stale_error();
     if (!d_u) return fail(c, LB_ERR_ARG, "lb_moments: d_u is NULL");
     prepare_fields(c);
-    launch_lattice(c->p.storage, c->P.G, 1, 0, c->pop(c->cur), nullptr, c->boxes(),
+    Geom G1 = c->P.G;
+    G1.tpb = 1;
+    launch_lattice(c->p.storage, G1, 1, 0, c->pop(c->cur), nullptr, c->boxes(),
                    total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), d_rho, d_u, c->stream);
     return check_async(c);
 }
@@ -615,7 +614,9 @@ int lb_diagnostics(lb_ctx* c, double* h_out)
     if (!h_out) return fail(c, LB_ERR_ARG, "h_out is NULL");
     prepare_fields(c);
     const Geom& G = c->P.G;
-    launch_lattice(c->p.storage, G, 2, 0, c->pop(c->cur), nullptr, c->boxes(), total_points(c) > 0 ? c->toff() : nullptr,
+    Geom G1 = G;
+    G1.tpb = 1;
+    launch_lattice(c->p.storage, G1, 2, 0, c->pop(c->cur), nullptr, c->boxes(), total_points(c) > 0 ? c->toff() : nullptr,
                    c->tlist(), c->rec(), c->diag(), nullptr, c->stream);
     launch_diag_reduce(G, c->diag(), c->diagout(), c->stream);
     int r = check_async(c);

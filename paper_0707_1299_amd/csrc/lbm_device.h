@@ -66,6 +66,8 @@ struct Geom {
     int ntx, nty, ntz;    // tiles per axis
     int maxp;             // max tiles touched by one point's stencil
     int bchunks;          // blocks per box of the per-box force / maximum reductions
+    int tpb;              // tiles per block of the step kernel
+    int pad2;
     long long N;          // nodes per box
     long long sp;         // elements between population planes
     long long sbox;       // elements between boxes (NQ * sp)

@@ -26,7 +26,8 @@ struct AdvectLaunch {
 
 bool tile_supported(int tx, int ty, int tz);
 bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
-                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s);
+                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_equilibrium(int storage, const Geom& G, void* dst, const BoxDev* boxes, const double* rho,
                         const double* u, hipStream_t s);
 

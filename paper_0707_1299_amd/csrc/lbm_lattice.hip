@@ -18,6 +18,8 @@
 // g is the force density spread from the tile's points with the Peskin kernel
 // (Sec. III) plus the optional uniform counter-force; u feeds the per-(tile,
 // point) interpolation partial sums of Sec. IV.
+#include <hip/hip_ext.h>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -41,18 +43,17 @@ template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_non
 // raw buffer accesses (scalar plane descriptor + 32-bit lane offset).
 // VAR bit 1: cached instead of non-temporal population loads.
 template <int ST, int TX, int TY, int TZ, int MODE, int VAR>
-__global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
-                                                   typename StoreT<ST>::S* __restrict__ dst,
-                                                   BoxDev* __restrict__ boxes, const int* __restrict__ toff,
-                                                   const int* __restrict__ tlist,
-                                                   const PRec<typename StoreT<ST>::T>* __restrict__ rec,
-                                                   double* __restrict__ out0, double* __restrict__ out1)
+__device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
+                                             const typename StoreT<ST>::S* __restrict__ src,
+                                             typename StoreT<ST>::S* __restrict__ dst, BoxDev* __restrict__ boxes,
+                                             const int* __restrict__ toff, const int* __restrict__ tlist,
+                                             const PRec<typename StoreT<ST>::T>* __restrict__ rec,
+                                             double* __restrict__ out0, double* __restrict__ out1)
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
     static_assert(TX * TY * TZ == BLOCK, "one node per thread");
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     int t = tile;
     const int itx = t % G.ntx;
     t /= G.ntx;
@@ -248,6 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
             __syncthreads();
             // per-tile maximum; the per-box reduction happens before the next step
             if (threadIdx.x == 0) ((float*)out1)[tile] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+            __syncthreads();   // wm is rewritten by the block's next tile
         }
         if (__any(bad) && lane == 0) atomicOr(&boxes[box].nonfinite, 1);
     }
@@ -283,6 +285,22 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
             __syncthreads();
         }
     }
+}
+
+// One block per run of G.tpb consecutive tiles (blocks renumbered so that the
+// runs of one XCD are contiguous); each tile is finished before the next.
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR>
+__global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
+                                                   typename StoreT<ST>::S* __restrict__ dst,
+                                                   BoxDev* __restrict__ boxes, const int* __restrict__ toff,
+                                                   const int* __restrict__ tlist,
+                                                   const PRec<typename StoreT<ST>::T>* __restrict__ rec,
+                                                   double* __restrict__ out0, double* __restrict__ out1)
+{
+    const int first = xcd_tile(blockIdx.x, gridDim.x) * G.tpb;
+    const int last = min((long long)first + G.tpb, G.ntiles);
+    for (int tile = first; tile < last; ++tile)
+        lattice_tile<ST, TX, TY, TZ, MODE, VAR>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1);
 }
 
 // Equilibrium of Eq. eqf at (rho, u) written so that the next pull sees it at
@@ -322,33 +340,41 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
 // ---------------------------------------------------------------------------
 // host-side launchers
 
+// With ev0/ev1 set, the runtime stamps the two events at the kernel's own start
+// and end (timing without the dispatch latency of separate event records).
 template <int ST, int TX, int TY, int TZ, int VAR>
 static void launch_step_v(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
-                          const void* rec, double* out0, double* out1, hipStream_t s)
+                          const void* rec, double* out0, double* out1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
-    hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR>), dim3((unsigned)G.ntiles), dim3(BLOCK), 0, s, G,
-                       (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1);
+    const unsigned nb = (unsigned)((G.ntiles + G.tpb - 1) / G.tpb);
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR>), dim3(nb), dim3(BLOCK), 0, s,
+                              ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0,
+                              out1);
+    else
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR>), dim3(nb), dim3(BLOCK), 0, s, G,
+                           (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1);
 }
 
 template <int ST, int TX, int TY, int TZ>
 static void launch_lattice_t(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
                              const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
-                             hipStream_t s)
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
-    const unsigned nblocks = (unsigned)G.ntiles;
+    const unsigned nblocks = (unsigned)((G.ntiles + G.tpb - 1) / G.tpb);
     auto a0 = (const S*)src;
     auto a1 = (S*)dst;
     auto r = (const PRec<T>*)rec;
     if (mode == M_STEP) {
         switch (variant & 3) {
-        case 1: launch_step_v<ST, TX, TY, TZ, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
-        case 2: launch_step_v<ST, TX, TY, TZ, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
-        case 3: launch_step_v<ST, TX, TY, TZ, 3>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
-        default: launch_step_v<ST, TX, TY, TZ, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s); break;
+        case 1: launch_step_v<ST, TX, TY, TZ, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
+        case 2: launch_step_v<ST, TX, TY, TZ, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
+        case 3: launch_step_v<ST, TX, TY, TZ, 3>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
+        default: launch_step_v<ST, TX, TY, TZ, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
         }
     } else if (mode == M_MOMENTS) {
         hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_MOMENTS, 0>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
@@ -362,11 +388,11 @@ static void launch_lattice_t(const Geom& G, int mode, int variant, const void* s
 template <int ST>
 static bool launch_lattice_s(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
                              const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
-                             hipStream_t s)
+                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
 #define LBM_TILE(X, Y, Z)                                                                                     \
     if (G.tx == X && G.ty == Y && G.tz == Z) {                                                                \
-        launch_lattice_t<ST, X, Y, Z>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);    \
+        launch_lattice_t<ST, X, Y, Z>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);    \
         return true;                                                                                          \
     }
     LBM_TILE(64, 2, 2)
@@ -392,12 +418,16 @@ bool tile_supported(int tx, int ty, int tz)
 }
 
 bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
-                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s)
+                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s,
+                    hipEvent_t ev0, hipEvent_t ev1)
 {
     switch (storage) {
-    case ST_FP64: return launch_lattice_s<ST_FP64>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);
-    case ST_FP32: return launch_lattice_s<ST_FP32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);
-    case ST_FP16: return launch_lattice_s<ST_FP16>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s);
+    case ST_FP64:
+        return launch_lattice_s<ST_FP64>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+    case ST_FP32:
+        return launch_lattice_s<ST_FP32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+    case ST_FP16:
+        return launch_lattice_s<ST_FP16>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
     }
     return false;
 }

@@ -22,7 +22,7 @@ CACHE = os.path.join(HERE, "tune_cache.json")
 ARCH = "gfx950"
 TILES = [(64, 2, 2), (64, 4, 1), (64, 1, 4), (128, 2, 1), (128, 1, 2), (256, 1, 1), (32, 4, 2), (32, 2, 4),
          (16, 4, 4)]
-VARIANTS = [0, 1, 2, 3]
+VARIANTS = [0, 2, 4, 6, 8, 10]
 
 
 def key(shape, storage, nboxes):

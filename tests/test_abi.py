@@ -51,7 +51,7 @@ def test_workspace_bytes_pure_and_monotone():
 
 @pytest.mark.parametrize("kw", [
     dict(shape=(3, 32, 32)), dict(shape=(32, 32, 2)), dict(nboxes=0), dict(storage=7),
-    dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=4), dict(variant=-1),
+    dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=16), dict(variant=-1),
 ])
 def test_bad_params_rejected(kw):
     args = dict(shape=(16, 16, 16), storage="fp32")

@@ -80,7 +80,8 @@ def test_stokeslet_32cubed_500_steps(storage):
 @pytest.mark.parametrize("storage,tile,variant", [
     ("fp64", None, 0), ("fp64", (16, 4, 4), 0), ("fp32", (32, 2, 4), 0), ("fp64", (64, 1, 4), 0),
     ("fp32", (128, 2, 1), 0), ("fp64", (64, 2, 2), 1), ("fp32", (64, 2, 2), 3), ("fp32", (128, 1, 2), 1),
-    ("fp64", (256, 1, 1), 3), ("fp32", (64, 4, 1), 2), ("fp32", (32, 4, 2), 3)])
+    ("fp64", (256, 1, 1), 3), ("fp32", (64, 4, 1), 2), ("fp32", (32, 4, 2), 3), ("fp64", (64, 2, 2), 4),
+    ("fp32", (128, 2, 1), 8), ("fp32", (32, 2, 4), 14), ("fp64", (16, 4, 4), 12)])
 def test_ragged_multi_tile_forces_zero_net(storage, tile, variant):
     """Non-cubic box with ragged tiles on every axis, forces near the periodic seams."""
     shape = (13, 10, 70)
@@ -221,7 +222,8 @@ def test_kernel_variants_bitwise_equal(storage):
     pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
     sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
     ref = None
-    for tile, variant in (((64, 2, 2), 0), ((64, 2, 2), 1), ((64, 2, 2), 2), ((64, 2, 2), 3), ((128, 2, 1), 1)):
+    for tile, variant in (((64, 2, 2), 0), ((64, 2, 2), 1), ((64, 2, 2), 2), ((64, 2, 2), 3), ((64, 2, 2), 4),
+                          ((64, 2, 2), 10), ((64, 2, 2), 12), ((128, 2, 1), 1)):
         _, u, o = run_gpu((L, L, L), storage, 0.5, sets, 12, tile=tile, variant=variant)
         if ref is None:
             ref = (u, o[0][1].cpu().numpy())
