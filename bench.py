@@ -22,7 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-BYTES_PER_NODE = {"fp64": 304, "fp32": 152, "fp16": 76}   # 2 x 19 populations x storage bytes
+# read + write of one node's stored state: 19 populations (fp64/fp32/fp16) or 10 FP32 moments
+BYTES_PER_NODE = {"fp64": 304, "fp32": 152, "fp16": 76, "mom32": 80}
 
 WORKLOADS = {
     # name: (shape, storage, tau, kind, n)
@@ -34,6 +35,10 @@ WORKLOADS = {
     "colloids256_fp64": ((256, 256, 256), "fp64", 0.5, "colloids", 10000),
     "colloids512_fp32": ((512, 512, 512), "fp32", 0.5, "colloids", 100000),
     "colloids512_fp16": ((512, 512, 512), "fp16", 0.5, "colloids", 100000),
+    "singularities128_mom32": ((128, 128, 128), "mom32", 0.5, "singularities", 64),
+    "boxes512x32_mom32": ((32, 32, 32), "mom32", None, "boxes", 512),
+    "colloids256_mom32": ((256, 256, 256), "mom32", 0.5, "colloids", 10000),
+    "colloids512_mom32": ((512, 512, 512), "mom32", 0.5, "colloids", 100000),
 }
 DESCR = {
     "singularities": "%d^3 periodic D3Q19 forced MRT, %s deviation storage, tau=1/2, %d seeded point "
@@ -236,7 +241,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32"}[storage],
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32", "mom32": "f32"}[storage],
         "data": "synthetic",
         "config": {"workload": describe(a.workload, r), "nodes": r["nodes"], "points": r["points"],
                    "seed": 20261200 + {"singularities": 2, "colloids": 3, "boxes": 4}[kind],

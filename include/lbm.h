@@ -58,6 +58,11 @@ extern "C" {
 #define LB_STORAGE_FP64 0 /* FP64 deviations, FP64 arithmetic */
 #define LB_STORAGE_FP32 1 /* FP32 deviations, FP32 arithmetic */
 #define LB_STORAGE_FP16 2 /* FP16 (fbar_i - w_i rho0)/w_i * 2^e per box, FP32 arithmetic */
+#define LB_STORAGE_MOM32 3 /* FP32 post-collision moments, 10 per node instead of 19
+                              populations (exact: with the ghosts projected out the
+                              post-collision state of Eq. fiexp is fixed by rho, A, B);
+                              FP32 arithmetic.  lb_set_equilibrium then sets the
+                              equilibrium as the previous step's post-collision state. */
 
 /* point-force set kinds */
 #define LB_FORCES_NEXT_STEP 0 /* applied in the next step only, then dropped */
@@ -87,7 +92,10 @@ typedef struct lb_params {
                                    plus 32-bit lane offsets,
                                2 = cached instead of non-temporal population loads,
                                4 * k (k = 0..3) = each block of the step kernel works
-                                   through 2^k consecutive tiles */
+                                   through 2^k consecutive tiles.
+                               With LB_STORAGE_MOM32 bits 0 and 1 have no effect: each
+                               node gathers the pieces of its 18 neighbours with cached
+                               buffer loads. */
 } lb_params;
 
 /*

@@ -26,7 +26,7 @@ constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-size_t storage_bytes(int st) { return st == LB_STORAGE_FP64 ? 8 : (st == LB_STORAGE_FP32 ? 4 : 2); }
+size_t storage_bytes(int st) { return st == LB_STORAGE_FP64 ? 8 : (st == LB_STORAGE_FP16 ? 2 : 4); }
 
 size_t rec_bytes(int st) { return st == LB_STORAGE_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>); }
 
@@ -67,7 +67,9 @@ void choose_tile(const lb_params* p, int& tx, int& ty, int& tz)
         tz = p->tile_z;
         return;
     }
-    if (p->nx >= 64) {
+    if (p->storage == LB_STORAGE_MOM32 && p->nx >= 128) {
+        tx = 128; ty = 1; tz = 2;   // long x rows: the gathered pieces are re-read from L1
+    } else if (p->nx >= 64) {
         tx = 64; ty = 2; tz = 2;
     } else if (p->nx >= 32) {
         tx = 32; ty = 4; tz = 2;
@@ -81,7 +83,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (!p) { why = "params is NULL"; return LB_ERR_ARG; }
     if (p->nx < 4 || p->ny < 4 || p->nz < 4) { why = "each of nx, ny, nz must be >= 4"; return LB_ERR_ARG; }
     if (p->nboxes < 1) { why = "nboxes must be >= 1"; return LB_ERR_ARG; }
-    if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_FP16) { why = "unknown storage"; return LB_ERR_ARG; }
+    if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_MOM32) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
     if (p->variant < 0 || p->variant > 15) { why = "unknown kernel variant"; return LB_ERR_ARG; }
@@ -97,7 +99,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.ntz = (p->nz + tz - 1) / tz;
     G.N = (long long)p->nx * p->ny * p->nz;
     G.sp = (G.N + 255) / 256 * 256 + 64;
-    G.sbox = (long long)NQ * G.sp;
+    G.sbox = (long long)planes_of(p->storage) * G.sp;
     G.tiles_per_box = (long long)G.ntx * G.nty * G.ntz;
     G.ntiles = G.tiles_per_box * p->nboxes;
     G.rho0 = p->rho0 > 0.0 ? p->rho0 : 1.0;

@@ -23,12 +23,21 @@ __host__ __device__ constexpr int cvel(int i, int a)
 
 __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
-enum Storage { ST_FP64 = 0, ST_FP32 = 1, ST_FP16 = 2 };
+enum Storage { ST_FP64 = 0, ST_FP32 = 1, ST_FP16 = 2, ST_MOM32 = 3 };
 
 template <int ST> struct StoreT;
 template <> struct StoreT<ST_FP64> { using S = double; using T = double; };
 template <> struct StoreT<ST_FP32> { using S = float; using T = float; };
 template <> struct StoreT<ST_FP16> { using S = _Float16; using T = float; };
+template <> struct StoreT<ST_MOM32> { using S = float; using T = float; };
+
+// Moment storage: with the ghosts projected out, the post-collision state of a
+// node is fixed by 10 numbers (Eq. fiexp); they are stored as the pieces of
+// the bracket f*_i / w_i = r0 + c_i.a + sum_a c_ia^2 b_aa + sum_{a<b} c_ia c_ib b_ab:
+//   r0 = drho - (3/2) tr B,  a = 3 A,  b_aa = (9/2) B_aa,  b_ab = 9 B_ab.
+enum MomPlane { MP_R0 = 0, MP_AX, MP_AY, MP_AZ, MP_BXX, MP_BYY, MP_BZZ, MP_BXY, MP_BXZ, MP_BYZ, MP_N };
+
+__host__ __device__ constexpr int planes_of(int st) { return st == ST_MOM32 ? MP_N : NQ; }
 
 // Entries of the per-tile point lists: point index and the index of this tile
 // among the tiles that point's stencil touches.
@@ -202,6 +211,47 @@ __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned off)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
     else
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, AUX);
+}
+
+// The 19 pre-collision populations of node (x, y, z) as deviations (for FP16
+// storage: deviation / w_i in units of the stored scale), pulled from the
+// post-collision data of the upstream nodes x - c_i.  xm/xp etc. are the
+// periodic neighbours of x, y, z.  The populations layout reads one value per
+// direction; the moment layout rebuilds each population from the upstream
+// node's stored bracket pieces.
+template <int ST, bool NTL>
+__device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restrict__ sb, long long sp, unsigned pbytes,
+                                          int ny, int nx, int x, int y, int z, int xm, int xp, int ym, int yp,
+                                          int zm, int zp, typename StoreT<ST>::T (&f)[NQ])
+{
+    using S = typename StoreT<ST>::S;
+    using T = typename StoreT<ST>::T;
+    constexpr int AUX = NTL ? 2 : 0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+        const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+        const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
+        const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
+        const unsigned off = ((unsigned(sz) * unsigned(ny) + unsigned(sy)) * unsigned(nx) + unsigned(sx)) * unsigned(sizeof(S));
+        if constexpr (ST == ST_MOM32) {
+            auto piece = [&](int k) { return bload<S, AUX>(plane_rsrc(sb + (long long)k * sp, pbytes), off); };
+            T br = piece(MP_R0);
+            if (cx != 0) br += (cx > 0 ? piece(MP_AX) : -piece(MP_AX)) + piece(MP_BXX);
+            if (cy != 0) br += (cy > 0 ? piece(MP_AY) : -piece(MP_AY)) + piece(MP_BYY);
+            if (cz != 0) br += (cz > 0 ? piece(MP_AZ) : -piece(MP_AZ)) + piece(MP_BZZ);
+            if (cx * cy != 0) br += cx * cy > 0 ? piece(MP_BXY) : -piece(MP_BXY);
+            if (cx * cz != 0) br += cx * cz > 0 ? piece(MP_BXZ) : -piece(MP_BXZ);
+            if (cy * cz != 0) br += cy * cz > 0 ? piece(MP_BYZ) : -piece(MP_BYZ);
+            f[i] = T(wgt(i)) * br;
+        } else {
+            const S v = bload<S, AUX>(plane_rsrc(sb + (long long)i * sp, pbytes), off);
+            if constexpr (ST == ST_FP16)
+                f[i] = float(v) * float(wgt(i));
+            else
+                f[i] = v;
+        }
+    }
 }
 
 // Wrap r into [0, L).

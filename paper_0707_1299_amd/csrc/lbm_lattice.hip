@@ -77,27 +77,25 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     // Each population plane is addressed as a wave-uniform buffer descriptor
     // plus a 32-bit per-lane byte offset (a plane holds < 4 GiB).
     constexpr bool WIDE = (VAR & 1);
-    constexpr bool NTL = !(VAR & 2);
+    // moment pieces are re-read by up to 18 neighbours: always cached loads
+    constexpr bool NTL = !(VAR & 2) && ST != ST_MOM32;
     const unsigned pbytes = unsigned(G.sp * (long long)sizeof(S));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T f[NQ];
+    if constexpr (WIDE && ST != ST_MOM32) {
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-        const int cx = cvel(i, 0);
-        const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
-        const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
-        const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
-        S v;
-        if constexpr (WIDE) {
-            v = ld<NTL>(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
-        } else {
-            const unsigned off = (unsigned(sz) * unsigned(G.ny) + unsigned(sy)) * unsigned(G.nx) + unsigned(sx);
-            v = bload<S, NTL ? 2 : 0>(plane_rsrc(sb + (long long)i * G.sp, pbytes), off * unsigned(sizeof(S)));
+        for (int i = 0; i < NQ; ++i) {
+            const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
+            const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
+            const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
+            const S v = ld<NTL>(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
+            if constexpr (ST == ST_FP16)
+                f[i] = float(v) * float(wgt(i));
+            else
+                f[i] = v;
         }
-        if constexpr (ST == ST_FP16)
-            f[i] = float(v) * float(wgt(i));
-        else
-            f[i] = v;
+    } else {
+        pull_node<ST, NTL>(sb, G.sp, pbytes, G.ny, G.nx, x, y, z, xm, xp, ym, yp, zm, zp, f);
     }
 
     // ---- moments (10 values)
@@ -215,21 +213,29 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         br[i] = base + T(3) * a + T(4.5) * q;
     }
 
-    // ---- store the post-collision populations at this node
+    // ---- store the post-collision state of this node
     S* db = dst + (long long)box * G.sbox;
     const unsigned n = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
     if (valid) {
+        if constexpr (ST == ST_MOM32) {
+            const T piece[MP_N] = {base, T(3) * ax, T(3) * ay, T(3) * az, T(4.5) * Bxx, T(4.5) * Byy, T(4.5) * Bzz,
+                                   T(9) * Bxy, T(9) * Bxz, T(9) * Byz};
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            S v;
-            if constexpr (ST == ST_FP16)
-                v = S(br[i] * B.s_out);
-            else
-                v = S(T(wgt(i)) * br[i]);
-            if constexpr (WIDE)
-                st(db + i * G.sp + (long long)n, v);
-            else
-                bstore<S, 2>(v, plane_rsrc(db + (long long)i * G.sp, pbytes), n * unsigned(sizeof(S)));
+            for (int k = 0; k < MP_N; ++k)
+                bstore<S, 2>(piece[k], plane_rsrc(db + (long long)k * G.sp, pbytes), n * unsigned(sizeof(S)));
+        } else {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                S v;
+                if constexpr (ST == ST_FP16)
+                    v = S(br[i] * B.s_out);
+                else
+                    v = S(T(wgt(i)) * br[i]);
+                if constexpr (WIDE)
+                    st(db + i * G.sp + (long long)n, v);
+                else
+                    bstore<S, 2>(v, plane_rsrc(db + (long long)i * G.sp, pbytes), n * unsigned(sizeof(S)));
+            }
         }
     }
 
@@ -303,6 +309,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
         lattice_tile<ST, TX, TY, TZ, MODE, VAR>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1);
 }
 
+
 // Equilibrium of Eq. eqf at (rho, u) written so that the next pull sees it at
 // every node: the copy held at node y for population i is the equilibrium of
 // node y + c_i.
@@ -319,6 +326,18 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
     const int x = int(n % G.nx), y = int((n / G.nx) % G.ny), z = int(n / ((long long)G.nx * G.ny));
     const double s = ST == ST_FP16 ? ldexp(1.0, boxes[box].e_data) : 1.0;
     S* db = dst + (long long)box * G.sbox;
+    if constexpr (ST == ST_MOM32) {
+        // the equilibrium of this node taken as its post-collision state
+        const double r = rho[(long long)box * G.N + n];
+        const double v[3] = {u[((long long)box * 3 + 0) * G.N + n], u[((long long)box * 3 + 1) * G.N + n],
+                             u[((long long)box * 3 + 2) * G.N + n]};
+        const double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double piece[MP_N] = {(r - G.rho0) - 1.5 * r * uu, 3 * r * v[0], 3 * r * v[1], 3 * r * v[2],
+                                    4.5 * r * v[0] * v[0], 4.5 * r * v[1] * v[1], 4.5 * r * v[2] * v[2],
+                                    9 * r * v[0] * v[1], 9 * r * v[0] * v[2], 9 * r * v[1] * v[2]};
+        for (int k = 0; k < MP_N; ++k) db[k * G.sp + n] = S(piece[k]);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         int xs = x + cvel(i, 0), ys = y + cvel(i, 1), zs = z + cvel(i, 2);
@@ -428,6 +447,8 @@ bool launch_lattice(int storage, const Geom& G, int mode, int variant, const voi
         return launch_lattice_s<ST_FP32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
     case ST_FP16:
         return launch_lattice_s<ST_FP16>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+    case ST_MOM32:
+        return launch_lattice_s<ST_MOM32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
     }
     return false;
 }
@@ -446,6 +467,9 @@ void launch_equilibrium(int storage, const Geom& G, void* dst, const BoxDev* box
         break;
     case ST_FP16:
         hipLaunchKernelGGL(k_equilibrium<ST_FP16>, dim3(nb), dim3(BLOCK), 0, s, G, (_Float16*)dst, boxes, rho, u);
+        break;
+    case ST_MOM32:
+        hipLaunchKernelGGL(k_equilibrium<ST_MOM32>, dim3(nb), dim3(BLOCK), 0, s, G, (float*)dst, boxes, rho, u);
         break;
     }
 }

@@ -444,14 +444,13 @@ __global__ __launch_bounds__(256) void k_interp_points(const Geom G, long long n
     const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z + 1 == G.nz ? 0 : z + 1;
     const auto* sb = src + (long long)box * G.sbox;
     const BoxDev& B = boxes[box];
+    T f[NQ];
+    pull_node<ST, false>(sb, G.sp, unsigned(G.sp * (long long)sizeof(*sb)), G.ny, G.nx, x, y, z, xm, xp, ym, yp, zm, zp,
+                         f);
     T drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-        const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
-        const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
-        const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
-        T v = T(sb[i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx]);
-        if constexpr (ST == ST_FP16) v *= T(wgt(i));
+        const T v = f[i];
         drho += v;
         if (cvel(i, 0) != 0) jx += cvel(i, 0) > 0 ? v : -v;
         if (cvel(i, 1) != 0) jy += cvel(i, 1) > 0 ? v : -v;
@@ -616,6 +615,10 @@ void launch_interp_points(int storage, const Geom& G, long long n, const double*
     case ST_FP16:
         hipLaunchKernelGGL(k_interp_points<ST_FP16>, dim3(nb), dim3(256), 0, s, G, n, pos, boxid, out,
                            (const _Float16*)src, boxes, toff, tlist, (const PRec<float>*)rec);
+        break;
+    case ST_MOM32:
+        hipLaunchKernelGGL(k_interp_points<ST_MOM32>, dim3(nb), dim3(256), 0, s, G, n, pos, boxid, out,
+                           (const float*)src, boxes, toff, tlist, (const PRec<float>*)rec);
         break;
     }
 }

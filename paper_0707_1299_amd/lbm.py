@@ -28,6 +28,7 @@ LB_ERR_STATE = -6
 LB_STORAGE_FP64 = 0
 LB_STORAGE_FP32 = 1
 LB_STORAGE_FP16 = 2
+LB_STORAGE_MOM32 = 3
 
 LB_FORCES_NEXT_STEP = 0
 LB_FORCES_STATIC = 1
@@ -36,7 +37,7 @@ LB_COLLOIDS = 2
 LB_NDIAG = 12
 LBML_NPARAM = 4545
 
-STORAGE = {"fp64": LB_STORAGE_FP64, "fp32": LB_STORAGE_FP32, "fp16": LB_STORAGE_FP16}
+STORAGE = {"fp64": LB_STORAGE_FP64, "fp32": LB_STORAGE_FP32, "fp16": LB_STORAGE_FP16, "mom32": LB_STORAGE_MOM32}
 
 
 class lb_params(ctypes.Structure):

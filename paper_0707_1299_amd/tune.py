@@ -39,7 +39,7 @@ def lookup(shape, storage, nboxes=1):
     return tuple(d["tile"]), int(d["variant"])
 
 
-def candidates(shape):
+def candidates(shape, storage="fp32"):
     nx = shape[2]
     out = []
     for t in TILES:
@@ -102,9 +102,9 @@ def tune(shape, storage, nboxes=1, steps=100, points=None, save=True, verbose=Tr
     """Sweep the candidates; the choice minimises the whole-step time (the fused kernel plus
     the point pipeline, which depends on how many tiles a point's stencil touches)."""
     N = shape[0] * shape[1] * shape[2] * nboxes
-    bpn = {"fp64": 304, "fp32": 152, "fp16": 76}[storage]
+    bpn = {"fp64": 304, "fp32": 152, "fp16": 76, "mom32": 80}[storage]
     res = []
-    for tile, variant in candidates(shape):
+    for tile, variant in candidates(shape, storage):
         ms, wall = measure(shape, storage, nboxes, tile, variant, steps, points)
         gbs = bpn * N / (ms * 1e-3) / 1e9
         res.append(dict(tile=list(tile), variant=variant, kernel_ms=ms, step_ms=wall, GBs=gbs))

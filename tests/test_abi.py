@@ -47,11 +47,15 @@ def test_workspace_bytes_pure_and_monotone():
     # two population copies of 19 planes dominate
     assert a >= 2 * 19 * 32 ** 3 * 4
     assert lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "fp32")) == a
+    # moment storage: two copies of 10 FP32 planes
+    m = lbm.lb_workspace_bytes(lbm.make_params((32, 32, 32), "mom32"))
+    assert 2 * 10 * 32 ** 3 * 4 <= m < a
 
 
 @pytest.mark.parametrize("kw", [
     dict(shape=(3, 32, 32)), dict(shape=(32, 32, 2)), dict(nboxes=0), dict(storage=7),
     dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=16), dict(variant=-1),
+    dict(storage="mom32", tile=(16, 8, 2)),
 ])
 def test_bad_params_rejected(kw):
     args = dict(shape=(16, 16, 16), storage="fp32")

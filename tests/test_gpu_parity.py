@@ -2,8 +2,10 @@
 
 Norm: max over nodes and components of |u_gpu - u_oracle| divided by
 max |u_oracle| (velocity field), and the same for interpolated velocities.
-Bars: 1e-10 for FP64 storage, 1e-5 for FP32 storage.  Both sides start from
-rest (or the same equilibrium) and receive the same seeded point forces.
+Bars: 1e-10 for FP64 storage, 1e-5 for FP32 storage and for FP32 moment
+storage (10 post-collision moments per node, exact in real arithmetic).  Both
+sides start from rest (or the same equilibrium) and receive the same seeded
+point forces.
 """
 import numpy as np
 import pytest
@@ -18,7 +20,7 @@ if not torch.cuda.is_available():
 
 from paper_0707_1299_amd import lbm, workloads  # noqa: E402
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "mom32": 1e-5}
 
 
 def dev(a, dtype=torch.float64):
@@ -62,7 +64,7 @@ def run_oracle(shape, tau, sets, steps, zero_net=False):
     return box, u
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
 def test_stokeslet_32cubed_500_steps(storage):
     """32^3, rho0 = 1 at rest, tau = 1/2 (nu = 1/6), one Stokeslet F = 1e-5 z, 500 steps."""
     pos, frc = workloads.stokeslet_box(32)
@@ -81,7 +83,9 @@ def test_stokeslet_32cubed_500_steps(storage):
     ("fp64", None, 0), ("fp64", (16, 4, 4), 0), ("fp32", (32, 2, 4), 0), ("fp64", (64, 1, 4), 0),
     ("fp32", (128, 2, 1), 0), ("fp64", (64, 2, 2), 1), ("fp32", (64, 2, 2), 3), ("fp32", (128, 1, 2), 1),
     ("fp64", (256, 1, 1), 3), ("fp32", (64, 4, 1), 2), ("fp32", (32, 4, 2), 3), ("fp64", (64, 2, 2), 4),
-    ("fp32", (128, 2, 1), 8), ("fp32", (32, 2, 4), 14), ("fp64", (16, 4, 4), 12)])
+    ("fp32", (128, 2, 1), 8), ("fp32", (32, 2, 4), 14), ("fp64", (16, 4, 4), 12), ("mom32", None, 0),
+    ("mom32", (16, 4, 4), 2), ("mom32", (64, 1, 4), 1), ("mom32", (128, 1, 2), 6), ("mom32", (32, 2, 4), 14),
+    ("mom32", (64, 2, 2), 8)])
 def test_ragged_multi_tile_forces_zero_net(storage, tile, variant):
     """Non-cubic box with ragged tiles on every axis, forces near the periodic seams."""
     shape = (13, 10, 70)
@@ -99,7 +103,7 @@ def test_ragged_multi_tile_forces_zero_net(storage, tile, variant):
     assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
 def test_multipoles(storage):
     """Stokeslets, stresslets and rotlets expanded by the library helper."""
     L = 40
@@ -113,7 +117,7 @@ def test_multipoles(storage):
     assert e <= TOL[storage]
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
 def test_colloids_advected(storage):
     """Sedimenting colloids: spread, interpolate, advance (a = 0.117, 1/a_L = 0.77)."""
     shape = (24, 20, 28)
@@ -135,9 +139,12 @@ def test_colloids_advected(storage):
     assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
 def test_equilibrium_start_and_moments(storage):
-    """Shear wave started from the Eq. eqf equilibrium; density and velocity after 40 steps."""
+    """Shear wave started from the Eq. eqf equilibrium; density and velocity after 40 steps.
+    Population storage starts the first collision from the equilibrium itself; moment storage
+    holds it as each node's previous post-collision state, so the first collision sees it
+    propagated once."""
     shape = (16, 12, 20)
     nz, ny, nx = shape
     z = np.arange(nz)[:, None, None] * np.ones(shape)
@@ -153,6 +160,8 @@ def test_equilibrium_start_and_moments(storage):
     lat.sync()
     box = oracle.Box(shape, 0.9)
     box.df = oracle.equilibrium(rho, u, 1.0)
+    if storage == "mom32":
+        box.df = oracle.stream(box.df)
     box.step(40)
     ro, uo = box.moments()
     assert rel(ug.cpu().numpy()[0], uo) <= TOL[storage]
@@ -160,7 +169,7 @@ def test_equilibrium_start_and_moments(storage):
     assert rel(r.cpu().numpy()[0] - 1.0, ro - 1.0) <= TOL[storage]
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
 def test_interp_velocity_at_arbitrary_points(storage):
     shape = (20, 20, 20)
     pos, frc = workloads.colloids(20, 5)
@@ -197,7 +206,7 @@ def test_batched_boxes_equal_single_runs_bitwise():
     L = 16
     w = workloads.mobility_boxes(nboxes=5, L=L, kmax=3)
     taus = w["taus"]
-    for storage in ("fp32", "fp64"):
+    for storage in ("fp32", "fp64", "mom32"):
         lat, ub, outs = run_gpu((L, L, L), storage, taus, [(w["pos"], w["force"], lbm.LB_FORCES_STATIC, None, w["box"])],
                                 70, zero_net=True, nboxes=5)
         Ub = outs[0][1].cpu().numpy()
@@ -214,7 +223,7 @@ def test_batched_boxes_equal_single_runs_bitwise():
                 assert rel(ub[b], uo) <= 1e-10
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "mom32"])
 def test_kernel_variants_bitwise_equal(storage):
     """The access variants move the same values: identical results bit for bit."""
     L = 128
@@ -222,14 +231,15 @@ def test_kernel_variants_bitwise_equal(storage):
     pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
     sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
     ref = None
-    for tile, variant in (((64, 2, 2), 0), ((64, 2, 2), 1), ((64, 2, 2), 2), ((64, 2, 2), 3), ((64, 2, 2), 4),
-                          ((64, 2, 2), 10), ((64, 2, 2), 12), ((128, 2, 1), 1)):
+    t0 = (64, 2, 2)
+    cases = ((t0, 0), (t0, 1), (t0, 2), (t0, 3), (t0, 4), (t0, 10), (t0, 12), ((128, 2, 1), 1))
+    for tile, variant in cases:
         _, u, o = run_gpu((L, L, L), storage, 0.5, sets, 12, tile=tile, variant=variant)
         if ref is None:
             ref = (u, o[0][1].cpu().numpy())
         else:
             assert np.array_equal(u, ref[0])
-            if tile == (64, 2, 2):     # interpolation partials are summed per tile: same tiling, same bits
+            if tile == t0:     # interpolation partials are summed per tile: same tiling, same bits
                 assert np.array_equal(o[0][1].cpu().numpy(), ref[1])
 
 
