@@ -4,11 +4,16 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Works on full auxiliary populations fbar (not deviations) and builds the
 collision matrix L explicitly:  L = M^-1 diag(lambda) M, where the rows of M
-are the moments {1, c, Q} and nine ghost moments chosen orthogonal to them in
-the w-weighted inner product.  Eigenvalues: 0 on mass and momentum (the
-conservation constraints of Eq. conservation), 1/tau on all six stress
-moments, 2/dt on the ghosts (so that (1 + L/2)^-1 L is the identity there,
-i.e. the ghosts are projected out).  One step is taken literally as
+are the moments 1, c, the trace of Q (bulk), five traceless combinations of
+Q (shear) and nine ghost moments chosen orthogonal to them in the w-weighted
+inner product.  Eigenvalues: 0 on mass and momentum (the conservation
+constraints of Eq. conservation), 1/tau on the shear moments, 1/tau_b on the
+bulk moment (tau_b = tau unless given), and lambda_g on the ghosts.  The
+paper's operator of Eq. fiexp is tau_b = tau, lambda_g = 2/dt (then
+(1 + L/2)^-1 L is the identity on the ghosts: they are projected out); the
+single-relaxation-time operator of Eq. bgklbe is tau_b = tau,
+lambda_g = 1/tau.  With one rate for all nine ghosts the operator does not
+depend on how the ghost subspace is spanned.  One step is taken literally as
 
     fbar(x + c_i, t + 1) = fbar(x, t) + (1 + L/2)^-1 [ -L (fbar - f0) + Phi ]
 
@@ -47,10 +52,11 @@ QT = np.einsum("ia,ib->iab", C, C) - CS2 * I3[None]  # Q_i tensor [19, 3, 3]
 
 
 def moment_matrix():
-    """Rows: 1, c_x, c_y, c_z, six stress components, nine w-orthogonal ghosts."""
-    rows = [np.ones(19), C[:, 0], C[:, 1], C[:, 2]]
-    for a, b in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)):
-        rows.append(QT[:, a, b])
+    """Rows: 1, c_x, c_y, c_z, the bulk moment tr Q, five traceless stress moments
+    (Q_xx - Q_yy, Q_xx + Q_yy - 2 Q_zz, Q_xy, Q_xz, Q_yz), nine w-orthogonal ghosts."""
+    rows = [np.ones(19), C[:, 0], C[:, 1], C[:, 2], QT[:, 0, 0] + QT[:, 1, 1] + QT[:, 2, 2],
+            QT[:, 0, 0] - QT[:, 1, 1], QT[:, 0, 0] + QT[:, 1, 1] - 2 * QT[:, 2, 2],
+            QT[:, 0, 1], QT[:, 0, 2], QT[:, 1, 2]]
     H = np.array(rows)                           # [10, 19]
     sw = np.sqrt(W)
     # orthogonal complement of span(sqrt(w) * h) in R^19, mapped back by 1/sqrt(w)
@@ -60,9 +66,10 @@ def moment_matrix():
     return np.vstack([H, ghosts])
 
 
-def collision_matrix(tau: float) -> np.ndarray:
+def collision_matrix(tau: float, tau_bulk: float | None = None, ghost_rate: float = 2.0) -> np.ndarray:
     M = moment_matrix()
-    lam = np.array([0.0] * 4 + [1.0 / tau] * 6 + [2.0] * 9)
+    tb = tau if tau_bulk is None else tau_bulk
+    lam = np.array([0.0] * 4 + [1.0 / tb] + [1.0 / tau] * 5 + [ghost_rate] * 9)
     return np.linalg.solve(M, np.diag(lam) @ M)
 
 
@@ -87,9 +94,9 @@ def physical_moments(fbar, g):
     return rho, v
 
 
-def collide(fbar, g, tau):
+def collide(fbar, g, tau, tau_bulk=None, ghost_rate=2.0):
     """Post-collision fbar* for every node; fbar [.., 19], g [.., 3]."""
-    L = collision_matrix(tau)
+    L = collision_matrix(tau, tau_bulk, ghost_rate)
     rho, v = physical_moments(fbar, g)
     f0 = equilibrium(rho, v)
     Phi = forcing(v, g)
@@ -165,9 +172,11 @@ def interp_dense(u, pos):
 class BruteBox:
     """Tiny periodic box stepped with the literal Eq. mrtlbe."""
 
-    def __init__(self, shape, tau, rho0=1.0):
+    def __init__(self, shape, tau, rho0=1.0, tau_bulk=None, ghost_rate=2.0):
         self.shape = tuple(shape)
         self.tau = tau
+        self.tau_bulk = tau_bulk
+        self.ghost_rate = ghost_rate
         self.rho0 = rho0
         self.fbar = np.broadcast_to(W * rho0, self.shape + (19,)).copy()
 
@@ -185,7 +194,7 @@ class BruteBox:
         return out
 
     def step(self, g):
-        self.fbar = stream(collide(self.fbar, g, self.tau))
+        self.fbar = stream(collide(self.fbar, g, self.tau, self.tau_bulk, self.ghost_rate))
 
     def moments(self, g):
         return physical_moments(self.fbar, g)
