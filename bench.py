@@ -39,6 +39,15 @@ WORKLOADS = {
     "boxes512x32_mom32": ((32, 32, 32), "mom32", None, "boxes", 512),
     "colloids256_mom32": ((256, 256, 256), "mom32", 0.5, "colloids", 10000),
     "colloids512_mom32": ((512, 512, 512), "mom32", 0.5, "colloids", 100000),
+    "singularities128_bgk": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
+    "singularities128_mrt": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
+    "singularities128_fp16_bgk": ((128, 128, 128), "fp16", 0.5, "singularities", 64),
+}
+# collision operator of a workload (default: the projected operator of Eq. fiexp)
+COLLISION = {
+    "singularities128_bgk": dict(collision="bgk"),
+    "singularities128_mrt": dict(collision="mrt", tau_bulk=1.0, ghost_rate=1.5),
+    "singularities128_fp16_bgk": dict(collision="bgk"),
 }
 DESCR = {
     "singularities": "%d^3 periodic D3Q19 forced MRT, %s deviation storage, tau=1/2, %d seeded point "
@@ -77,15 +86,16 @@ def tuned(shape, storage, nboxes=1):
     return tune.lookup(shape, storage, nboxes) or (None, 0)
 
 
-def build_lattice(shape, storage, tau, kind, pos, frc, model):
+def build_lattice(shape, storage, tau, kind, pos, frc, model, opts=None):
     import torch
     from paper_0707_1299_amd import lbm
+    opts = opts or {}
     if kind == "boxes":
         w = pos
         nb = len(w["taus"])
         tile, variant = tuned(shape, storage, nb)
         lat = lbm.Lattice(shape, storage, nboxes=nb, tau=w["taus"], zero_net_force=True, max_points=len(w["pos"]),
-                          tile=tile, variant=variant)
+                          tile=tile, variant=variant, **opts)
         p = torch.tensor(w["pos"], dtype=torch.float64, device="cuda")
         vsum = torch.zeros_like(p)
         lat.add_point_forces(p, torch.tensor(w["force"], dtype=torch.float64, device="cuda"),
@@ -94,7 +104,7 @@ def build_lattice(shape, storage, tau, kind, pos, frc, model):
         return lat, p
     tile, variant = tuned(shape, storage)
     lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "colloid"), max_points=len(pos), tile=tile,
-                      variant=variant)
+                      variant=variant, **opts)
     p = torch.tensor(pos, dtype=torch.float64, device="cuda")
     f = torch.tensor(frc, dtype=torch.float64, device="cuda")
     if kind == "colloid":
@@ -158,7 +168,7 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
         model = dict(model, mlp_seed=0)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model)
+        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, COLLISION.get(name))
         lat.step(warmup)
         lat.sync()
         torch.cuda.synchronize()
@@ -190,10 +200,15 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
 def describe(name, r):
     shape, storage, tau, kind, n = WORKLOADS[name]
     if kind == "singularities":
-        return DESCR[kind] % (shape[0], storage, n, r["points"])
-    if kind == "boxes":
-        return DESCR[kind] % (n, shape[0], storage, r["points"])
-    return DESCR[kind] % (shape[0], storage, n)
+        d = DESCR[kind] % (shape[0], storage, n, r["points"])
+    elif kind == "boxes":
+        d = DESCR[kind] % (n, shape[0], storage, r["points"])
+    else:
+        d = DESCR[kind] % (shape[0], storage, n)
+    c = COLLISION.get(name)
+    if c:
+        d += ", collision %s" % ", ".join("%s=%s" % kv for kv in sorted(c.items()))
+    return d
 
 
 def main():
@@ -255,13 +270,13 @@ def main():
     if "colloid_updates_per_s" in r:
         out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)
 
-    if not a.no_cpu and kind != "boxes":
+    if not a.no_cpu and kind != "boxes" and a.workload not in COLLISION:
         box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
         out["cpu_baseline"] = cb
         # same number of steps on a fresh GPU lattice: error of this storage against the oracle
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            lat2, _ = build_lattice(shape, storage, tau, fkind, pos, frc, model)
+            lat2, _ = build_lattice(shape, storage, tau, fkind, pos, frc, model, COLLISION.get(a.workload))
             lat2.step(csteps)
             _, u = lat2.moments(rho=False)
             lat2.sync()
@@ -274,7 +289,11 @@ def main():
         for name, steps, mlp in (("colloids256_fp32", 300, False), ("colloids256_fp16", 300, False),
                                  ("colloids256_fp64", 200, False), ("colloids512_fp32", 100, False),
                                  ("colloids512_fp16", 100, False), ("colloids512_fp16", 100, True),
-                                 ("boxes512x32_fp32", 300, False), ("boxes512x32_fp16", 300, False)):
+                                 ("boxes512x32_fp32", 300, False), ("boxes512x32_fp16", 300, False),
+                                 ("singularities128_mom32", 2000, False), ("colloids256_mom32", 300, False),
+                                 ("colloids512_mom32", 100, False), ("boxes512x32_mom32", 300, False),
+                                 ("singularities128_bgk", 2000, False), ("singularities128_mrt", 2000, False),
+                                 ("singularities128_fp16_bgk", 2000, False)):
             rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
             rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
             extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)

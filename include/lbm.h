@@ -64,6 +64,13 @@ extern "C" {
                               FP32 arithmetic.  lb_set_equilibrium then sets the
                               equilibrium as the previous step's post-collision state. */
 
+/* collision operators (lb_params.collision) */
+#define LB_COLLISION_PROJECTED 0 /* Eq. fiexp: ghosts projected out, stress modes at 1/tau */
+#define LB_COLLISION_BGK 1       /* Eq. bgklbe: every mode relaxes at 1/tau (ghosts kept) */
+#define LB_COLLISION_MRT 2       /* Eq. mrtlbe with eigenvalues 1/tau on the five shear
+                                    modes, 1/tau_bulk on the bulk mode and ghost_rate on
+                                    all nine ghost modes */
+
 /* point-force set kinds */
 #define LB_FORCES_NEXT_STEP 0 /* applied in the next step only, then dropped */
 #define LB_FORCES_STATIC 1    /* applied every step at fixed positions */
@@ -96,6 +103,14 @@ typedef struct lb_params {
                                With LB_STORAGE_MOM32 bits 0 and 1 have no effect: each
                                node gathers the pieces of its 18 neighbours with cached
                                buffer loads. */
+    int32_t collision;      /* LB_COLLISION_*; 0 = projected (the paper's operator) */
+    const double* tau_bulk; /* LB_COLLISION_MRT: HOST array [nboxes] (> 0), read during
+                               lb_init only; NULL = tau */
+    double ghost_rate;      /* LB_COLLISION_MRT: eigenvalue of the ghost modes, in (0, 4];
+                               a ghost moment is multiplied by (1 - r/2)/(1 + r/2) per
+                               step; 2 projects them out.  LB_STORAGE_MOM32 keeps no
+                               ghosts and accepts only collisions that project them out
+                               (projected, or MRT with ghost_rate = 2). */
 } lb_params;
 
 /*

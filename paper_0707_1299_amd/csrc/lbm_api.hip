@@ -87,6 +87,19 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
     if (p->variant < 0 || p->variant > 15) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if (p->collision < LB_COLLISION_PROJECTED || p->collision > LB_COLLISION_MRT) {
+        why = "unknown collision operator";
+        return LB_ERR_ARG;
+    }
+    if (p->collision == LB_COLLISION_MRT && !(p->ghost_rate > 0.0 && p->ghost_rate <= 4.0)) {
+        why = "ghost_rate must be in (0, 4]";
+        return LB_ERR_ARG;
+    }
+    if (p->storage == LB_STORAGE_MOM32 &&
+        (p->collision == LB_COLLISION_BGK || (p->collision == LB_COLLISION_MRT && p->ghost_rate != 2.0))) {
+        why = "moment storage keeps no ghost moments: the collision must project them out";
+        return LB_ERR_ARG;
+    }
     int tx, ty, tz;
     choose_tile(p, tx, ty, tz);
     if (!tile_supported(tx, ty, tz)) { why = "unsupported tile shape"; return LB_ERR_ARG; }
@@ -113,6 +126,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (G.maxp > (1 << PK_BITS)) { why = "tile too small for the stencil"; return LB_ERR_ARG; }
     G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
     G.tpb = 1 << ((p->variant >> 2) & 3);
+    G.coll = p->collision != LB_COLLISION_PROJECTED;
     P.chunks = G.bchunks;
     Layout& L = P.L;
     size_t o = 0;
@@ -392,6 +406,10 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     if (!p->tau) return fail(nullptr, LB_ERR_ARG, "tau is NULL");
     for (int b = 0; b < p->nboxes; ++b)
         if (!(p->tau[b] > 0.0) || !isfinite(p->tau[b])) return fail(nullptr, LB_ERR_ARG, "tau must be finite and > 0");
+    if (p->collision == LB_COLLISION_MRT && p->tau_bulk)
+        for (int b = 0; b < p->nboxes; ++b)
+            if (!(p->tau_bulk[b] > 0.0) || !isfinite(p->tau_bulk[b]))
+                return fail(nullptr, LB_ERR_ARG, "tau_bulk must be finite and > 0");
     if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0)
         return fail(nullptr, LB_ERR_ARG, "workspace NULL or not 256-byte aligned");
     if (bytes < P.L.total) return fail(nullptr, LB_ERR_SIZE, "workspace too small");
@@ -399,6 +417,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->p = *p;
     c->tau.assign(p->tau, p->tau + p->nboxes);
     c->p.tau = c->tau.data();
+    c->p.tau_bulk = nullptr;   // read below, not kept
     c->P = P;
     c->ws = (char*)d_workspace;
     c->stream = (hipStream_t)hip_stream;
@@ -419,6 +438,12 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
         memset(&B, 0, sizeof(B));
         B.tau = p->tau[b];
         B.omega = 1.0 / (p->tau[b] + 0.5);
+        B.tau_b = (p->collision == LB_COLLISION_MRT && p->tau_bulk) ? p->tau_bulk[b] : p->tau[b];
+        B.omega_b = 1.0 / (B.tau_b + 0.5);
+        // eigenvalue r of a ghost mode: the moment is multiplied by (1 - r/2) / (1 + r/2)
+        const double r = p->collision == LB_COLLISION_BGK ? 1.0 / p->tau[b]
+                         : p->collision == LB_COLLISION_MRT ? p->ghost_rate : 2.0;
+        B.kappa_g = (1.0 - 0.5 * r) / (1.0 + 0.5 * r);
         B.e_data = e0;
         B.s_in = ldexpf(1.0f, -e0);
         B.s_out = ldexpf(1.0f, e0);

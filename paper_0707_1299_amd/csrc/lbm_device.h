@@ -60,6 +60,9 @@ struct alignas(16) BoxDev {
     double tau;
     double omega;      // 1 / (tau + 1/2)
     double gc[3];      // uniform counter-force density (zero unless requested)
+    double tau_b;      // bulk relaxation time (general collision)
+    double omega_b;    // 1 / (tau_b + 1/2)
+    double kappa_g;    // ghost moments are multiplied by this per step (0: projected out)
     float s_in;        // FP16: dequantise multiplier 2^-e of the stored data
     float s_out;       // FP16: quantise multiplier 2^e of the data written this step
     int e_data;        // FP16: exponent of the data currently stored
@@ -76,7 +79,7 @@ struct Geom {
     int maxp;             // max tiles touched by one point's stencil
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
-    int pad2;
+    int coll;             // 1: general collision (bulk rate, ghost moments kept)
     long long N;          // nodes per box
     long long sp;         // elements between population planes
     long long sbox;       // elements between boxes (NQ * sp)

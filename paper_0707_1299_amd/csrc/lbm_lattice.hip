@@ -42,7 +42,9 @@ template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_non
 // VAR bit 0: global loads/stores with 64-bit per-lane addresses instead of
 // raw buffer accesses (scalar plane descriptor + 32-bit lane offset).
 // VAR bit 1: cached instead of non-temporal population loads.
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR>
+// COLL: general collision of Eq. mrtlbe (bulk mode at its own rate, ghost
+// moments multiplied by kappa_g instead of projected out).
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
 __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                                              const typename StoreT<ST>::S* __restrict__ src,
                                              typename StoreT<ST>::S* __restrict__ dst, BoxDev* __restrict__ boxes,
@@ -191,9 +193,24 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const T third = T(1.0 / 3.0);
     const T sxx = pxx - drho * third, syy = pyy - drho * third, szz = pzz - drho * third;
     const T tau = T(B.tau), om = T(B.omega);
-    const T Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
-    const T Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
-    const T Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
+    T Bxx, Byy, Bzz;
+    if constexpr (COLL) {
+        // shear drivers of the diagonal; their trace relaxes at omega_b instead (bulk mode)
+        const T dxx = sxx - rho * ux * ux - tau * (T(2) * ux * gx);
+        const T dyy = syy - rho * uy * uy - tau * (T(2) * uy * gy);
+        const T dzz = szz - rho * uz * uz - tau * (T(2) * uz * gz);
+        const T trs = (dxx + dyy + dzz) * third;
+        const T tb = T(B.tau_b), omb = T(B.omega_b);
+        const T trb = (sxx + syy + szz - rho * (ux * ux + uy * uy + uz * uz) -
+                       tb * (T(2) * (ux * gx + uy * gy + uz * gz))) * third;
+        Bxx = sxx - om * (dxx - trs) - omb * trb;
+        Byy = syy - om * (dyy - trs) - omb * trb;
+        Bzz = szz - om * (dzz - trs) - omb * trb;
+    } else {
+        Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
+        Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
+        Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
+    }
     const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
     const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
     const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
@@ -211,6 +228,28 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         if (cx * cz != 0) q += cx * cz > 0 ? T(2) * Bxz : T(-2) * Bxz;
         if (cy * cz != 0) q += cy * cz > 0 ? T(2) * Byz : T(-2) * Byz;
         br[i] = base + T(3) * a + T(4.5) * q;
+    }
+    if constexpr (COLL && ST != ST_MOM32) {
+        // ghost part of the pulled state (deviation minus its projection onto 1, c, Q),
+        // carried over with factor kappa_g; added here in units of w_i
+        const T kg = T(B.kappa_g);
+        const T hbase = drho - T(1.5) * (sxx + syy + szz);
+        T s_in = T(1);
+        if constexpr (ST == ST_FP16) s_in = T(B.s_in);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+            T a = 0, q = 0;
+            if (cx != 0) { a += cx > 0 ? jx : -jx; q += sxx; }
+            if (cy != 0) { a += cy > 0 ? jy : -jy; q += syy; }
+            if (cz != 0) { a += cz > 0 ? jz : -jz; q += szz; }
+            if (cx * cy != 0) q += cx * cy > 0 ? T(2) * pxy : T(-2) * pxy;
+            if (cx * cz != 0) q += cx * cz > 0 ? T(2) * pxz : T(-2) * pxz;
+            if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
+            const T hb = hbase + T(3) * a + T(4.5) * q;
+            const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
+            br[i] += kg * (f[i] * s_in * inv_w - hb);
+        }
     }
 
     // ---- store the post-collision state of this node
@@ -295,7 +334,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 
 // One block per run of G.tpb consecutive tiles (blocks renumbered so that the
 // runs of one XCD are contiguous); each tile is finished before the next.
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR>
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
 __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
                                                    BoxDev* __restrict__ boxes, const int* __restrict__ toff,
@@ -306,7 +345,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
     const int first = xcd_tile(blockIdx.x, gridDim.x) * G.tpb;
     const int last = min((long long)first + G.tpb, G.ntiles);
     for (int tile = first; tile < last; ++tile)
-        lattice_tile<ST, TX, TY, TZ, MODE, VAR>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1);
+        lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1);
 }
 
 
@@ -361,20 +400,30 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
 
 // With ev0/ev1 set, the runtime stamps the two events at the kernel's own start
 // and end (timing without the dispatch latency of separate event records).
-template <int ST, int TX, int TY, int TZ, int VAR>
-static void launch_step_v(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
+template <int ST, int TX, int TY, int TZ, int VAR, int COLL>
+static void launch_step_c(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
                           const void* rec, double* out0, double* out1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
     const unsigned nb = (unsigned)((G.ntiles + G.tpb - 1) / G.tpb);
     if (ev0 && ev1)
-        hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR>), dim3(nb), dim3(BLOCK), 0, s,
+        hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s,
                               ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0,
                               out1);
     else
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR>), dim3(nb), dim3(BLOCK), 0, s, G,
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s, G,
                            (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1);
+}
+
+template <int ST, int TX, int TY, int TZ, int VAR>
+static void launch_step_v(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
+                          const void* rec, double* out0, double* out1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (G.coll)
+        launch_step_c<ST, TX, TY, TZ, VAR, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+    else
+        launch_step_c<ST, TX, TY, TZ, VAR, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
 }
 
 template <int ST, int TX, int TY, int TZ>

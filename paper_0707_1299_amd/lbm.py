@@ -30,6 +30,11 @@ LB_STORAGE_FP32 = 1
 LB_STORAGE_FP16 = 2
 LB_STORAGE_MOM32 = 3
 
+LB_COLLISION_PROJECTED = 0
+LB_COLLISION_BGK = 1
+LB_COLLISION_MRT = 2
+COLLISION = {"projected": LB_COLLISION_PROJECTED, "bgk": LB_COLLISION_BGK, "mrt": LB_COLLISION_MRT}
+
 LB_FORCES_NEXT_STEP = 0
 LB_FORCES_STATIC = 1
 LB_COLLOIDS = 2
@@ -48,6 +53,8 @@ class lb_params(ctypes.Structure):
         ("max_points", ctypes.c_int64),
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
         ("fp16_exponent", ctypes.c_int32), ("variant", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("tau_bulk", ctypes.POINTER(ctypes.c_double)),
+        ("ghost_rate", ctypes.c_double),
     ]
 
 
@@ -128,8 +135,8 @@ def _stream_handle():
 
 
 def make_params(shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_force=False, max_points=0,
-                tile=None, fp16_exponent=0, variant=0):
-    """lb_params for boxes of shape (nz, ny, nx); tau is a scalar or a per-box sequence."""
+                tile=None, fp16_exponent=0, variant=0, collision="projected", tau_bulk=None, ghost_rate=2.0):
+    """lb_params for boxes of shape (nz, ny, nx); tau and tau_bulk are scalars or per-box sequences."""
     nz, ny, nx = shape
     taus = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, dtype=np.float64), (nboxes,)))
     p = lb_params()
@@ -144,7 +151,13 @@ def make_params(shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_for
         p.tile_x, p.tile_y, p.tile_z = tile
     p.fp16_exponent = fp16_exponent
     p.variant = variant
+    p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
+    p.ghost_rate = ghost_rate
     p._taus = taus  # keep alive
+    if tau_bulk is not None:
+        tb = np.ascontiguousarray(np.broadcast_to(np.asarray(tau_bulk, dtype=np.float64), (nboxes,)))
+        p.tau_bulk = tb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p._tau_bulk = tb
     return p
 
 
@@ -202,13 +215,14 @@ class Lattice:
     """One liblbm context on the current torch device and stream."""
 
     def __init__(self, shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_force=False, max_points=0,
-                 tile=None, fp16_exponent=0, variant=0, stream=None):
+                 tile=None, fp16_exponent=0, variant=0, stream=None, collision="projected", tau_bulk=None,
+                 ghost_rate=2.0):
         import torch
         self.torch = torch
         self.shape = tuple(shape)
         self.nboxes = nboxes
         self.params = make_params(shape, storage, nboxes, tau, rho0, zero_net_force, max_points, tile,
-                                  fp16_exponent, variant)
+                                  fp16_exponent, variant, collision, tau_bulk, ghost_rate)
         nbytes = lb_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
