@@ -42,12 +42,17 @@ WORKLOADS = {
     "singularities128_bgk": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
     "singularities128_mrt": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
     "singularities128_fp16_bgk": ((128, 128, 128), "fp16", 0.5, "singularities", 64),
+    "singularities128_thermal": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
+    "colloids256_thermal": ((256, 256, 256), "fp32", 0.5, "colloids", 10000),
 }
-# collision operator of a workload (default: the projected operator of Eq. fiexp)
-COLLISION = {
+# lattice options of a workload: collision operator (default: the projected operator of
+# Eq. fiexp) and thermal noise
+OPTS = {
     "singularities128_bgk": dict(collision="bgk"),
     "singularities128_mrt": dict(collision="mrt", tau_bulk=1.0, ghost_rate=1.5),
     "singularities128_fp16_bgk": dict(collision="bgk"),
+    "singularities128_thermal": dict(kT=1e-5, seed=7),
+    "colloids256_thermal": dict(kT=1e-5, seed=7),
 }
 DESCR = {
     "singularities": "%d^3 periodic D3Q19 forced MRT, %s deviation storage, tau=1/2, %d seeded point "
@@ -61,7 +66,7 @@ DESCR = {
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lbm_lattice.hip", "lbm_device.h"):
+    for f in ("lbm_lattice_impl.h", "lbm_device.h", "lbm_noise.h"):
         h.update(open(os.path.join(ROOT, "paper_0707_1299_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -168,7 +173,7 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
         model = dict(model, mlp_seed=0)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, COLLISION.get(name))
+        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(name))
         lat.step(warmup)
         lat.sync()
         torch.cuda.synchronize()
@@ -205,9 +210,9 @@ def describe(name, r):
         d = DESCR[kind] % (n, shape[0], storage, r["points"])
     else:
         d = DESCR[kind] % (shape[0], storage, n)
-    c = COLLISION.get(name)
+    c = OPTS.get(name)
     if c:
-        d += ", collision %s" % ", ".join("%s=%s" % kv for kv in sorted(c.items()))
+        d += ", %s" % ", ".join("%s=%s" % kv for kv in sorted(c.items()))
     return d
 
 
@@ -270,13 +275,13 @@ def main():
     if "colloid_updates_per_s" in r:
         out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)
 
-    if not a.no_cpu and kind != "boxes" and a.workload not in COLLISION:
+    if not a.no_cpu and kind != "boxes" and a.workload not in OPTS:
         box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
         out["cpu_baseline"] = cb
         # same number of steps on a fresh GPU lattice: error of this storage against the oracle
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
-            lat2, _ = build_lattice(shape, storage, tau, fkind, pos, frc, model, COLLISION.get(a.workload))
+            lat2, _ = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(a.workload))
             lat2.step(csteps)
             _, u = lat2.moments(rho=False)
             lat2.sync()
@@ -293,7 +298,8 @@ def main():
                                  ("singularities128_mom32", 2000, False), ("colloids256_mom32", 300, False),
                                  ("colloids512_mom32", 100, False), ("boxes512x32_mom32", 300, False),
                                  ("singularities128_bgk", 2000, False), ("singularities128_mrt", 2000, False),
-                                 ("singularities128_fp16_bgk", 2000, False)):
+                                 ("singularities128_fp16_bgk", 2000, False), ("singularities128_thermal", 2000, False),
+                                 ("colloids256_thermal", 300, False)):
             rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
             rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
             extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)

@@ -111,6 +111,21 @@ typedef struct lb_params {
                                step; 2 projects them out.  LB_STORAGE_MOM32 keeps no
                                ghosts and accepts only collisions that project them out
                                (projected, or MRT with ghost_rate = 2). */
+    double kT;              /* thermal energy (lattice units); 0 = deterministic.  > 0: the
+                               fluctuating step (Sec. II): after the collision each
+                               non-conserved mode k (bulk, five shear, nine ghost
+                               polynomials of the orthogonal D3Q19 basis) receives a
+                               Gaussian increment of variance (kT/cs^2) rho b_k
+                               (1 - gamma_k^2), b_k its norm, gamma_k the factor the
+                               collision applies to its non-equilibrium part (ghosts
+                               therefore carry noise even when projected); LB_COLLOIDS
+                               sets also receive the extra displacement of Appendix B,
+                               variance kT/(3 pi eta)(1/a - 1/a_L) per step.  Not with
+                               LB_STORAGE_MOM32. */
+    uint64_t seed;          /* key of the Philox4x32-10 generator of the noise; the
+                               draws of step t depend only on (seed, t, node or point
+                               index), so a run is reproducible and independent of
+                               tiles, variants, graphs and batching */
 } lb_params;
 
 /*

@@ -47,8 +47,8 @@ int max_axis_tiles(int n, int t)
 }
 
 struct Layout {
-    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, pslot, partial, fpart, pmax, tmax, ticket, err, diag,
-        diagout;
+    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, pslot, partial, fpart, pmax, tmax, ticket, tctr, err,
+        diag, diagout;
     size_t total;
 };
 
@@ -100,6 +100,11 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
         why = "moment storage keeps no ghost moments: the collision must project them out";
         return LB_ERR_ARG;
     }
+    if (!(p->kT >= 0.0) || !isfinite(p->kT)) { why = "kT must be finite and >= 0"; return LB_ERR_ARG; }
+    if (p->storage == LB_STORAGE_MOM32 && p->kT > 0.0) {
+        why = "moment storage keeps no ghost moments: thermal noise needs population storage";
+        return LB_ERR_ARG;
+    }
     int tx, ty, tz;
     choose_tile(p, tx, ty, tz);
     if (!tile_supported(tx, ty, tz)) { why = "unsupported tile shape"; return LB_ERR_ARG; }
@@ -126,7 +131,9 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (G.maxp > (1 << PK_BITS)) { why = "tile too small for the stencil"; return LB_ERR_ARG; }
     G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
     G.tpb = 1 << ((p->variant >> 2) & 3);
-    G.coll = p->collision != LB_COLLISION_PROJECTED;
+    G.coll = p->kT > 0.0 ? 2 : (p->collision != LB_COLLISION_PROJECTED ? 1 : 0);
+    G.seed_lo = uint32_t(p->seed);
+    G.seed_hi = uint32_t(p->seed >> 32);
     P.chunks = G.bchunks;
     Layout& L = P.L;
     size_t o = 0;
@@ -147,6 +154,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.pmax = take(sizeof(float) * p->nboxes * P.chunks);
     L.tmax = take(sizeof(float) * G.ntiles);
     L.ticket = take(sizeof(unsigned) * p->nboxes);
+    L.tctr = take(2 * sizeof(unsigned long long));
     L.err = take(sizeof(int) * 4);
     L.diag = take(sizeof(double) * LBD_N * G.ntiles);
     L.diagout = take(sizeof(double) * LBD_N * p->nboxes);
@@ -209,6 +217,7 @@ struct lb_ctx {
     float* pmax() const { return (float*)(ws + P.L.pmax); }
     float* tmax() const { return (float*)(ws + P.L.tmax); }
     unsigned* ticket() const { return (unsigned*)(ws + P.L.ticket); }
+    unsigned long long* tctr() const { return (unsigned long long*)(ws + P.L.tctr); }
     int* errw() const { return (int*)(ws + P.L.err); }
     double* diag() const { return (double*)(ws + P.L.diag); }
     double* diagout() const { return (double*)(ws + P.L.diagout); }
@@ -299,8 +308,11 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
         e1 = c->ev[c->ev_used++];
         c->timed_launches++;
     }
+    unsigned long long* tin = G.coll == 2 ? c->tctr() + c->cur : nullptr;
+    unsigned long long* tout = G.coll == 2 ? c->tctr() + (c->cur ^ 1) : nullptr;
     launch_lattice(c->p.storage, G, 0, c->p.variant, c->pop(c->cur), c->pop(c->cur ^ 1), c->boxes(),
-                   npts > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), c->partial(), (double*)c->tmax(), s, e0, e1);
+                   npts > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), c->partial(), (double*)c->tmax(), tin, tout,
+                   s, e0, e1);
     long long off = 0;
     for (auto& st : c->sets) {
         const bool adv = st.kind == LB_COLLOIDS;
@@ -314,6 +326,7 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
             a.pos = (double*)st.pos;
             a.boxid = st.box;
             a.advect = adv ? 1 : 0;
+            a.tin = adv ? tin : nullptr;
             if (st.has_model) {
                 a.vel_out = st.model.d_vel_out;
                 a.vel_sum = st.model.d_vel_sum;
@@ -444,6 +457,15 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
         const double r = p->collision == LB_COLLISION_BGK ? 1.0 / p->tau[b]
                          : p->collision == LB_COLLISION_MRT ? p->ghost_rate : 2.0;
         B.kappa_g = (1.0 - 0.5 * r) / (1.0 + 0.5 * r);
+        // thermal noise: a mode whose non-equilibrium part is multiplied by gamma receives
+        // variance mu rho b (1 - gamma^2), mu = kT / cs^2
+        const double mu = 3.0 * p->kT;
+        const double gb = 1.0 - B.omega_b, gs = 1.0 - B.omega, gg = B.kappa_g;
+        B.nz_b = sqrt(mu * (1.0 - gb * gb));
+        B.nz_s = sqrt(mu * (1.0 - gs * gs));
+        B.nz_g = sqrt(mu * (1.0 - gg * gg));
+        const double eta = P.G.rho0 * p->tau[b] / 3.0;
+        B.pn = p->kT / (3.0 * M_PI * eta);
         B.e_data = e0;
         B.s_in = ldexpf(1.0f, -e0);
         B.s_out = ldexpf(1.0f, e0);
@@ -457,6 +479,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     launch_fill_u32(c->cursor(), G.ntiles, 0u, s);
     launch_fill_u32(c->toff(), G.ntiles + 1, 0u, s);
     launch_fill_u32(c->ticket(), p->nboxes, 0u, s);
+    launch_fill_u32(c->tctr(), 4, 0u, s);
     launch_fill_u32(c->tmax(), G.ntiles, 0u, s);
     launch_fill_u32(c->errw(), 4, 0u, s);
     r = hip_check(c, hipMemcpyAsync(c->boxes(), c->hboxes.data(), sizeof(BoxDev) * p->nboxes, hipMemcpyHostToDevice, s),
@@ -592,7 +615,8 @@ int lb_moments(lb_ctx* c, double* d_rho, double* d_u)
     Geom G1 = c->P.G;
     G1.tpb = 1;
     launch_lattice(c->p.storage, G1, 1, 0, c->pop(c->cur), nullptr, c->boxes(),
-                   total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), d_rho, d_u, c->stream);
+                   total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->rec(), d_rho, d_u, nullptr, nullptr,
+                   c->stream);
     return check_async(c);
 }
 
@@ -644,7 +668,7 @@ int lb_diagnostics(lb_ctx* c, double* h_out)
     Geom G1 = G;
     G1.tpb = 1;
     launch_lattice(c->p.storage, G1, 2, 0, c->pop(c->cur), nullptr, c->boxes(), total_points(c) > 0 ? c->toff() : nullptr,
-                   c->tlist(), c->rec(), c->diag(), nullptr, c->stream);
+                   c->tlist(), c->rec(), c->diag(), nullptr, nullptr, nullptr, c->stream);
     launch_diag_reduce(G, c->diag(), c->diagout(), c->stream);
     int r = check_async(c);
     if (r) return r;

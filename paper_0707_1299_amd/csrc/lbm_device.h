@@ -63,6 +63,10 @@ struct alignas(16) BoxDev {
     double tau_b;      // bulk relaxation time (general collision)
     double omega_b;    // 1 / (tau_b + 1/2)
     double kappa_g;    // ghost moments are multiplied by this per step (0: projected out)
+    double nz_b;       // thermal noise: sqrt(mu (1 - gamma^2)) of the bulk mode (mu = kT / cs^2)
+    double nz_s;       // ... of the shear modes
+    double nz_g;       // ... of the ghost modes
+    double pn;         // particle noise: variance kT / (3 pi eta) per unit of 1/a - 1/a_L
     float s_in;        // FP16: dequantise multiplier 2^-e of the stored data
     float s_out;       // FP16: quantise multiplier 2^e of the data written this step
     int e_data;        // FP16: exponent of the data currently stored
@@ -79,7 +83,8 @@ struct Geom {
     int maxp;             // max tiles touched by one point's stencil
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
-    int coll;             // 1: general collision (bulk rate, ghost moments kept)
+    int coll;             // 1: general collision (bulk rate, ghost moments kept); 2: with thermal noise
+    unsigned seed_lo, seed_hi;   // key of the noise generator
     long long N;          // nodes per box
     long long sp;         // elements between population planes
     long long sbox;       // elements between boxes (NQ * sp)

@@ -22,12 +22,14 @@ struct AdvectLaunch {
     const uint16_t* mlp;
     float in_shift[4], in_scale[4], out_scale;
     int advect;
+    const unsigned long long* tin;   // thermal runs: step counter of this step (else NULL)
 };
 
 bool tile_supported(int tx, int ty, int tz);
 bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
-                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s,
-                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
+                    const unsigned long long* tin, unsigned long long* tout, hipStream_t s, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
 void launch_equilibrium(int storage, const Geom& G, void* dst, const BoxDev* boxes, const double* rho,
                         const double* u, hipStream_t s);
 

@@ -1,353 +1,23 @@
-// Lattice kernels: the fused forced-MRT step and the moment / diagnostic
-// passes that share its per-node arithmetic.
-//
-// One thread per node, one 256-thread block per tile of TX x TY x TZ nodes
-// (x fastest, one wave64 per x-row segment).  The step is a pull scheme:
-// node x gathers population i from x - c_i of the source copy (the
-// propagation of Sec. II), collides in registers and writes its own 19
-// post-collision populations to the destination copy.  Populations are kept
-// as deviations from w_i rho0; the FP16 mode stores (deviation / w_i) * 2^e.
-//
-// Collision, per node (Eq. fiexp and the A, B that follow it; ghosts projected
-// out, every stress mode relaxed with omega = 1/(tau + 1/2)):
-//   drho = sum df_i,  j = sum df_i c_i,  S = sum df_i (c_i c_i - I/3)
-//   rho = rho0 + drho,  u = (j + g/2) / rho              (Eq. macrovariables2)
-//   A = j + g
-//   B = S - omega (S - rho u u - tau (u g + g u))       (sign from Eq. mrtlbe)
-//   df*_i = w_i [ drho + 3 A.c_i + 9/2 B:(c_i c_i - I/3) ]
-// g is the force density spread from the tile's points with the Peskin kernel
-// (Sec. III) plus the optional uniform counter-force; u feeds the per-(tile,
-// point) interpolation partial sums of Sec. IV.
-#include <hip/hip_ext.h>
-
+// Lattice entry points: storage dispatch of the step / moment / diagnostic
+// kernels (instantiated in lbm_lattice_<storage>.hip from lbm_lattice_impl.h),
+// the equilibrium initialisation and the tile shapes they support.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
 namespace lbm {
 
-enum Mode { M_STEP = 0, M_MOMENTS = 1, M_DIAG = 2 };
-
-constexpr int CHUNK = 32;  // points reduced per LDS round in the interpolation
-
-template <bool NT, class S> __device__ __forceinline__ S ld(const S* p)
-{
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_nontemporal_store(v, p); }
-
-// VAR bit 0: global loads/stores with 64-bit per-lane addresses instead of
-// raw buffer accesses (scalar plane descriptor + 32-bit lane offset).
-// VAR bit 1: cached instead of non-temporal population loads.
-// COLL: general collision of Eq. mrtlbe (bulk mode at its own rate, ghost
-// moments multiplied by kappa_g instead of projected out).
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
-__device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
-                                             const typename StoreT<ST>::S* __restrict__ src,
-                                             typename StoreT<ST>::S* __restrict__ dst, BoxDev* __restrict__ boxes,
-                                             const int* __restrict__ toff, const int* __restrict__ tlist,
-                                             const PRec<typename StoreT<ST>::T>* __restrict__ rec,
-                                             double* __restrict__ out0, double* __restrict__ out1)
-{
-    using S = typename StoreT<ST>::S;
-    using T = typename StoreT<ST>::T;
-    static_assert(TX * TY * TZ == BLOCK, "one node per thread");
-
-    int t = tile;
-    const int itx = t % G.ntx;
-    t /= G.ntx;
-    const int ity = t % G.nty;
-    t /= G.nty;
-    const int itz = t % G.ntz;
-    const int box = t / G.ntz;
-    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-    const int x0 = itx * TX + lx, y0 = ity * TY + ly, z0 = itz * TZ + lz;
-    const bool valid = (x0 < G.nx) & (y0 < G.ny) & (z0 < G.nz);
-    // threads past a ragged edge work on a clamped in-range node and contribute nothing
-    const int x = min(x0, G.nx - 1), y = min(y0, G.ny - 1), z = min(z0, G.nz - 1);
-    const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x + 1 == G.nx ? 0 : x + 1;
-    const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y + 1 == G.ny ? 0 : y + 1;
-    const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z + 1 == G.nz ? 0 : z + 1;
-
-    const BoxDev& B = boxes[box];
-    const S* sb = src + (long long)box * G.sbox;
-
-    // ---- pull: population i at x comes from x - c_i
-    // Each population plane is addressed as a wave-uniform buffer descriptor
-    // plus a 32-bit per-lane byte offset (a plane holds < 4 GiB).
-    constexpr bool WIDE = (VAR & 1);
-    // moment pieces are re-read by up to 18 neighbours: always cached loads
-    constexpr bool NTL = !(VAR & 2) && ST != ST_MOM32;
-    const unsigned pbytes = unsigned(G.sp * (long long)sizeof(S));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    T f[NQ];
-    if constexpr (WIDE && ST != ST_MOM32) {
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
-            const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
-            const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
-            const S v = ld<NTL>(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
-            if constexpr (ST == ST_FP16)
-                f[i] = float(v) * float(wgt(i));
-            else
-                f[i] = v;
-        }
-    } else {
-        pull_node<ST, NTL>(sb, G.sp, pbytes, G.ny, G.nx, x, y, z, xm, xp, ym, yp, zm, zp, f);
-    }
-
-    // ---- moments (10 values)
-    T drho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-        const T v = f[i];
-        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-        drho += v;
-        if (cx != 0) { jx += cx > 0 ? v : -v; pxx += v; }
-        if (cy != 0) { jy += cy > 0 ? v : -v; pyy += v; }
-        if (cz != 0) { jz += cz > 0 ? v : -v; pzz += v; }
-        if (cx * cy != 0) pxy += cx * cy > 0 ? v : -v;
-        if (cx * cz != 0) pxz += cx * cz > 0 ? v : -v;
-        if (cy * cz != 0) pyz += cy * cz > 0 ? v : -v;
-    }
-    if constexpr (ST == ST_FP16) {
-        const T s = MODE == M_STEP ? T(B.s_in) : T(ldexpf(1.0f, -B.e_data));
-        drho *= s; jx *= s; jy *= s; jz *= s;
-        pxx *= s; pyy *= s; pzz *= s; pxy *= s; pxz *= s; pyz *= s;
-    }
-
-    // ---- force density at this node: counter-force + the tile's points
-    T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
-    int k0 = 0, k1 = 0;
-    if (toff) {
-        k0 = toff[tile];
-        k1 = toff[tile + 1];
-    }
-    for (int k = k0; k < k1; ++k) {
-        const PRec<T>& r = rec[pk_point(tlist[k])];
-        const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
-                    stencil_w<T>(z, r.bz, G.nz, r.wz);
-        gx += r.f[0] * w;
-        gy += r.f[1] * w;
-        gz += r.f[2] * w;
-    }
-
-    const T rho = T(G.rho0) + drho;
-    const T ir = T(1) / rho;
-    const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
-
-    if constexpr (MODE == M_MOMENTS) {
-        if (valid) {
-            const long long n = ((long long)z * G.ny + y) * G.nx + x;
-            if (out0) out0[(long long)box * G.N + n] = G.rho0 + double(drho);
-            out1[((long long)box * 3 + 0) * G.N + n] = double(ux);
-            out1[((long long)box * 3 + 1) * G.N + n] = double(uy);
-            out1[((long long)box * 3 + 2) * G.N + n] = double(uz);
-        }
-        return;
-    }
-
-    if constexpr (MODE == M_DIAG) {
-        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + pxy + pxz + pyz + gx + gy + gz;
-        const bool bad = !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
-        double v[LBD_N];
-        const double X = x, Y = y, Z = z;
-        v[0] = drho; v[1] = jx; v[2] = jy; v[3] = jz;
-        v[4] = gx; v[5] = gy; v[6] = gz;
-        v[7] = Y * double(gz) - Z * double(gy);
-        v[8] = Z * double(gx) - X * double(gz);
-        v[9] = X * double(gy) - Y * double(gx);
-        v[10] = sqrt(double(ux) * ux + double(uy) * uy + double(uz) * uz);
-        v[11] = bad ? 1.0 : 0.0;
-        __shared__ double red[4][LBD_N];
-#pragma unroll
-        for (int c = 0; c < LBD_N; ++c) {
-            double a = valid ? v[c] : 0.0;
-            if (c == 10) {
-                if (!(a == a)) a = 0.0;  // max ignores NaN; the count reports it
-                a = wave_max(a);
-            } else {
-                a = wave_sum(a);
-            }
-            if (lane == 0) red[wave][c] = a;
-        }
-        __syncthreads();
-        if (threadIdx.x < LBD_N) {
-            const int c = threadIdx.x;
-            double a;
-            if (c == 10)
-                a = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
-            else
-                a = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-            out0[(long long)tile * LBD_N + c] = a;
-        }
-        return;
-    }
-
-    // ---- M_STEP: collide
-    const T ax = jx + gx, ay = jy + gy, az = jz + gz;
-    const T third = T(1.0 / 3.0);
-    const T sxx = pxx - drho * third, syy = pyy - drho * third, szz = pzz - drho * third;
-    const T tau = T(B.tau), om = T(B.omega);
-    T Bxx, Byy, Bzz;
-    if constexpr (COLL) {
-        // shear drivers of the diagonal; their trace relaxes at omega_b instead (bulk mode)
-        const T dxx = sxx - rho * ux * ux - tau * (T(2) * ux * gx);
-        const T dyy = syy - rho * uy * uy - tau * (T(2) * uy * gy);
-        const T dzz = szz - rho * uz * uz - tau * (T(2) * uz * gz);
-        const T trs = (dxx + dyy + dzz) * third;
-        const T tb = T(B.tau_b), omb = T(B.omega_b);
-        const T trb = (sxx + syy + szz - rho * (ux * ux + uy * uy + uz * uz) -
-                       tb * (T(2) * (ux * gx + uy * gy + uz * gz))) * third;
-        Bxx = sxx - om * (dxx - trs) - omb * trb;
-        Byy = syy - om * (dyy - trs) - omb * trb;
-        Bzz = szz - om * (dzz - trs) - omb * trb;
-    } else {
-        Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
-        Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
-        Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
-    }
-    const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
-    const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
-    const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
-    const T base = drho - T(1.5) * (Bxx + Byy + Bzz);
-
-    T br[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-        T a = 0, q = 0;
-        if (cx != 0) { a += cx > 0 ? ax : -ax; q += Bxx; }
-        if (cy != 0) { a += cy > 0 ? ay : -ay; q += Byy; }
-        if (cz != 0) { a += cz > 0 ? az : -az; q += Bzz; }
-        if (cx * cy != 0) q += cx * cy > 0 ? T(2) * Bxy : T(-2) * Bxy;
-        if (cx * cz != 0) q += cx * cz > 0 ? T(2) * Bxz : T(-2) * Bxz;
-        if (cy * cz != 0) q += cy * cz > 0 ? T(2) * Byz : T(-2) * Byz;
-        br[i] = base + T(3) * a + T(4.5) * q;
-    }
-    if constexpr (COLL && ST != ST_MOM32) {
-        // ghost part of the pulled state (deviation minus its projection onto 1, c, Q),
-        // carried over with factor kappa_g; added here in units of w_i
-        const T kg = T(B.kappa_g);
-        const T hbase = drho - T(1.5) * (sxx + syy + szz);
-        T s_in = T(1);
-        if constexpr (ST == ST_FP16) s_in = T(B.s_in);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-            T a = 0, q = 0;
-            if (cx != 0) { a += cx > 0 ? jx : -jx; q += sxx; }
-            if (cy != 0) { a += cy > 0 ? jy : -jy; q += syy; }
-            if (cz != 0) { a += cz > 0 ? jz : -jz; q += szz; }
-            if (cx * cy != 0) q += cx * cy > 0 ? T(2) * pxy : T(-2) * pxy;
-            if (cx * cz != 0) q += cx * cz > 0 ? T(2) * pxz : T(-2) * pxz;
-            if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
-            const T hb = hbase + T(3) * a + T(4.5) * q;
-            const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
-            br[i] += kg * (f[i] * s_in * inv_w - hb);
-        }
-    }
-
-    // ---- store the post-collision state of this node
-    S* db = dst + (long long)box * G.sbox;
-    const unsigned n = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
-    if (valid) {
-        if constexpr (ST == ST_MOM32) {
-            const T piece[MP_N] = {base, T(3) * ax, T(3) * ay, T(3) * az, T(4.5) * Bxx, T(4.5) * Byy, T(4.5) * Bzz,
-                                   T(9) * Bxy, T(9) * Bxz, T(9) * Byz};
-#pragma unroll
-            for (int k = 0; k < MP_N; ++k)
-                bstore<S, 2>(piece[k], plane_rsrc(db + (long long)k * G.sp, pbytes), n * unsigned(sizeof(S)));
-        } else {
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) {
-                S v;
-                if constexpr (ST == ST_FP16)
-                    v = S(br[i] * B.s_out);
-                else
-                    v = S(T(wgt(i)) * br[i]);
-                if constexpr (WIDE)
-                    st(db + i * G.sp + (long long)n, v);
-                else
-                    bstore<S, 2>(v, plane_rsrc(db + (long long)i * G.sp, pbytes), n * unsigned(sizeof(S)));
-            }
-        }
-    }
-
-    // ---- health: non-finite values; FP16 range and the max for rescaling
-    {
-        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
-        bool bad = valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
-        if constexpr (ST == ST_FP16) {
-            T m = 0;
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) m = fmax(m, fabs(br[i]));
-            if (!valid) m = 0;
-            bad = bad || (m * B.s_out > T(65504));
-            m = wave_max(m);
-            __shared__ float wm[4];
-            if (lane == 0) wm[wave] = m;
-            __syncthreads();
-            // per-tile maximum; the per-box reduction happens before the next step
-            if (threadIdx.x == 0) ((float*)out1)[tile] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
-            __syncthreads();   // wm is rewritten by the block's next tile
-        }
-        if (__any(bad) && lane == 0) atomicOr(&boxes[box].nonfinite, 1);
-    }
-
-    // ---- interpolation partial sums: sum over this tile's nodes of u * deltaP(x - R)
-    if (k1 > k0) {
-        __shared__ T red[4][CHUNK][3];
-        for (int c0 = k0; c0 < k1; c0 += CHUNK) {
-            const int cn = min(CHUNK, k1 - c0);
-            for (int kk = 0; kk < cn; ++kk) {
-                const PRec<T>& r = rec[pk_point(tlist[c0 + kk])];
-                T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
-                      stencil_w<T>(z, r.bz, G.nz, r.wz);
-                if (!valid) w = T(0);
-                T sx = 0, sy = 0, sz = 0;
-                if (__any(w != T(0))) {
-                    sx = wave_sum(ux * w);
-                    sy = wave_sum(uy * w);
-                    sz = wave_sum(uz * w);
-                }
-                if (lane == 0) {
-                    red[wave][kk][0] = sx;
-                    red[wave][kk][1] = sy;
-                    red[wave][kk][2] = sz;
-                }
-            }
-            __syncthreads();
-            if (threadIdx.x < 3 * cn) {
-                const int kk = threadIdx.x / 3, c = threadIdx.x % 3;
-                out0[(long long)(c0 + kk) * 3 + c] =
-                    ((double(red[0][kk][c]) + double(red[1][kk][c])) + double(red[2][kk][c])) + double(red[3][kk][c]);
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// One block per run of G.tpb consecutive tiles (blocks renumbered so that the
-// runs of one XCD are contiguous); each tile is finished before the next.
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
-__global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
-                                                   typename StoreT<ST>::S* __restrict__ dst,
-                                                   BoxDev* __restrict__ boxes, const int* __restrict__ toff,
-                                                   const int* __restrict__ tlist,
-                                                   const PRec<typename StoreT<ST>::T>* __restrict__ rec,
-                                                   double* __restrict__ out0, double* __restrict__ out1)
-{
-    const int first = xcd_tile(blockIdx.x, gridDim.x) * G.tpb;
-    const int last = min((long long)first + G.tpb, G.ntiles);
-    for (int tile = first; tile < last; ++tile)
-        lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1);
-}
-
+bool launch_lattice_fp64(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                          const int* tlist, const void* rec, double* out0, double* out1, const unsigned long long* tin,
+                          unsigned long long* tout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+bool launch_lattice_fp32(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                          const int* tlist, const void* rec, double* out0, double* out1, const unsigned long long* tin,
+                          unsigned long long* tout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+bool launch_lattice_fp16(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                          const int* tlist, const void* rec, double* out0, double* out1, const unsigned long long* tin,
+                          unsigned long long* tout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+bool launch_lattice_mom32(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes, const int* toff,
+                          const int* tlist, const void* rec, double* out0, double* out1, const unsigned long long* tin,
+                          unsigned long long* tout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 
 // Equilibrium of Eq. eqf at (rho, u) written so that the next pull sees it at
 // every node: the copy held at node y for population i is the equilibrium of
@@ -395,87 +65,6 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
     }
 }
 
-// ---------------------------------------------------------------------------
-// host-side launchers
-
-// With ev0/ev1 set, the runtime stamps the two events at the kernel's own start
-// and end (timing without the dispatch latency of separate event records).
-template <int ST, int TX, int TY, int TZ, int VAR, int COLL>
-static void launch_step_c(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
-                          const void* rec, double* out0, double* out1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
-{
-    using S = typename StoreT<ST>::S;
-    using T = typename StoreT<ST>::T;
-    const unsigned nb = (unsigned)((G.ntiles + G.tpb - 1) / G.tpb);
-    if (ev0 && ev1)
-        hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s,
-                              ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0,
-                              out1);
-    else
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s, G,
-                           (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1);
-}
-
-template <int ST, int TX, int TY, int TZ, int VAR>
-static void launch_step_v(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
-                          const void* rec, double* out0, double* out1, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
-{
-    if (G.coll)
-        launch_step_c<ST, TX, TY, TZ, VAR, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
-    else
-        launch_step_c<ST, TX, TY, TZ, VAR, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
-}
-
-template <int ST, int TX, int TY, int TZ>
-static void launch_lattice_t(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
-                             const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
-                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
-{
-    using S = typename StoreT<ST>::S;
-    using T = typename StoreT<ST>::T;
-    const unsigned nblocks = (unsigned)((G.ntiles + G.tpb - 1) / G.tpb);
-    auto a0 = (const S*)src;
-    auto a1 = (S*)dst;
-    auto r = (const PRec<T>*)rec;
-    if (mode == M_STEP) {
-        switch (variant & 3) {
-        case 1: launch_step_v<ST, TX, TY, TZ, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
-        case 2: launch_step_v<ST, TX, TY, TZ, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
-        case 3: launch_step_v<ST, TX, TY, TZ, 3>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
-        default: launch_step_v<ST, TX, TY, TZ, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1); break;
-        }
-    } else if (mode == M_MOMENTS) {
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_MOMENTS, 0>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
-                           boxes, toff, tlist, r, out0, out1);
-    } else {
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_DIAG, 0>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
-                           boxes, toff, tlist, r, out0, out1);
-    }
-}
-
-template <int ST>
-static bool launch_lattice_s(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
-                             const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
-                             hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
-{
-#define LBM_TILE(X, Y, Z)                                                                                     \
-    if (G.tx == X && G.ty == Y && G.tz == Z) {                                                                \
-        launch_lattice_t<ST, X, Y, Z>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);    \
-        return true;                                                                                          \
-    }
-    LBM_TILE(64, 2, 2)
-    LBM_TILE(64, 4, 1)
-    LBM_TILE(64, 1, 4)
-    LBM_TILE(32, 4, 2)
-    LBM_TILE(32, 2, 4)
-    LBM_TILE(16, 4, 4)
-    LBM_TILE(128, 2, 1)
-    LBM_TILE(128, 1, 2)
-    LBM_TILE(256, 1, 1)
-#undef LBM_TILE
-    return false;
-}
-
 bool tile_supported(int tx, int ty, int tz)
 {
     const int ok[][3] = {{64, 2, 2}, {64, 4, 1}, {64, 1, 4}, {32, 4, 2}, {32, 2, 4},
@@ -486,18 +75,23 @@ bool tile_supported(int tx, int ty, int tz)
 }
 
 bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
-                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1, hipStream_t s,
-                    hipEvent_t ev0, hipEvent_t ev1)
+                    const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
+                    const unsigned long long* tin, unsigned long long* tout, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1)
 {
     switch (storage) {
     case ST_FP64:
-        return launch_lattice_s<ST_FP64>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+        return launch_lattice_fp64(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
+                                   ev1);
     case ST_FP32:
-        return launch_lattice_s<ST_FP32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+        return launch_lattice_fp32(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
+                                   ev1);
     case ST_FP16:
-        return launch_lattice_s<ST_FP16>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+        return launch_lattice_fp16(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
+                                   ev1);
     case ST_MOM32:
-        return launch_lattice_s<ST_MOM32>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, s, ev0, ev1);
+        return launch_lattice_mom32(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
+                                    ev1);
     }
     return false;
 }

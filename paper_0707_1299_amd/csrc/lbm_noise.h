@@ -1,0 +1,95 @@
+// Thermal noise of the fluctuating step and of the Brownian colloid update.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds that multiply counter words 0 and 2 by 0xD2511F53 and 0xCD9E8D57,
+// mix the high halves of the products with the other counter words and the
+// key, and advance the key by 0x9E3779B9, 0xBB67AE85 between rounds.
+// Normals: Box-Muller on pairs of 32-bit outputs, u = (x + 1/2) 2^-32,
+// z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = sqrt(-2 ln u0) sin(2 pi u1).
+//
+// Modes: the fifteen non-conserved D3Q19 polynomials of the orthogonal basis
+// of Duenweg, Schiller and Ladd (2007), mutually w-orthogonal and orthogonal
+// to 1 and c: bulk, five shear, nine ghosts (see emode).
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+struct Philox4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+
+template <class T> __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, T& z0, T& z1)
+{
+    constexpr T two_m32 = T(2.3283064365386962890625e-10);   // 2^-32
+    const T u0 = (T(a) + T(0.5)) * two_m32, u1 = (T(b) + T(0.5)) * two_m32;
+    const T r = sqrt(T(-2) * log(u0));
+    const T t = T(2.0 * 3.14159265358979323846) * u1;
+    z0 = r * cos(t);
+    z1 = r * sin(t);
+}
+
+// The fifteen mode polynomials at velocity i (integers on D3Q19).
+__host__ __device__ constexpr int emode(int k, int i)
+{
+    const int x = cvel(i, 0), y = cvel(i, 1), z = cvel(i, 2);
+    const int c2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return c2 - 1;                          // bulk
+    case 1: return 3 * x * x - c2;                  // shear
+    case 2: return y * y - z * z;
+    case 3: return x * y;
+    case 4: return x * z;
+    case 5: return y * z;
+    case 6: return (3 * c2 - 5) * x;                // ghosts
+    case 7: return (3 * c2 - 5) * y;
+    case 8: return (3 * c2 - 5) * z;
+    case 9: return (y * y - z * z) * x;
+    case 10: return (z * z - x * x) * y;
+    case 11: return (x * x - y * y) * z;
+    case 12: return 3 * c2 * c2 - 6 * c2 + 1;
+    case 13: return (2 * c2 - 3) * (3 * x * x - c2);
+    default: return (2 * c2 - 3) * (y * y - z * z);
+    }
+}
+
+// b_k = sum_i w_i e_k(c_i)^2
+__host__ __device__ constexpr double mode_norm(int k)
+{
+    double b = 0.0;
+    for (int i = 0; i < NQ; ++i) b += wgt(i) * double(emode(k, i) * emode(k, i));
+    return b;
+}
+
+// Counter words of the node noise: call j of step t for node n of box b.
+__device__ __forceinline__ Philox4 node_draw(uint32_t n, uint32_t b, unsigned long long t, uint32_t j, uint32_t k0,
+                                             uint32_t k1)
+{
+    return philox4x32_10(n, b, uint32_t(t), ((uint32_t(t >> 32) & 0x0FFFFFFFu) << 4) | j, k0, k1);
+}
+
+// ... and of the particle noise of point p (stream word 2^32 - 1, never a box index).
+__device__ __forceinline__ Philox4 particle_draw(uint32_t p, unsigned long long t, uint32_t k0, uint32_t k1)
+{
+    return philox4x32_10(p, 0xFFFFFFFFu, uint32_t(t), (uint32_t(t >> 32) & 0x0FFFFFFFu) << 4, k0, k1);
+}
+
+}  // namespace lbm

@@ -11,6 +11,7 @@
 
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include "lbm_noise.h"
 
 namespace lbm {
 
@@ -328,6 +329,7 @@ struct AdvectArgs {
     const uint16_t* mlp;
     float in_shift[4], in_scale[4], out_scale;
     int advect;
+    const unsigned long long* tin;
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
@@ -401,7 +403,18 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
         inv_aL += double(A.out_scale) * double(mlp_eval(W, xin));
     }
     const double mob = (A.inv_a - inv_aL) / (6.0 * M_PI * eta);
-    for (int a = 0; a < 3; ++a) A.pos[3 * i + a] = wrap_pos(R[a] + U[a] + A.frc[3 * i + a] * mob, L[a]);
+    double zeta[3] = {0.0, 0.0, 0.0};
+    if (A.tin) {
+        // Appendix B: extra Brownian displacement, variance kT/(3 pi eta)(1/a - 1/a_L) per step
+        const Philox4 q = particle_draw(uint32_t(p), *A.tin, G.seed_lo, G.seed_hi);
+        double z[4];
+        box_muller<double>(q.v[0], q.v[1], z[0], z[1]);
+        box_muller<double>(q.v[2], q.v[3], z[2], z[3]);
+        const double amp = sqrt(boxes[box].pn * fmax(A.inv_a - inv_aL, 0.0));
+        for (int a = 0; a < 3; ++a) zeta[a] = amp * z[a];
+    }
+    for (int a = 0; a < 3; ++a)
+        A.pos[3 * i + a] = wrap_pos(R[a] + (U[a] + zeta[a]) + A.frc[3 * i + a] * mob, L[a]);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,6 +607,7 @@ void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, co
     }
     A.out_scale = a.out_scale;
     A.advect = a.advect;
+    A.tin = a.tin;
     hipLaunchKernelGGL(k_advect, dim3(nblk(a.n, 256)), dim3(256), 0, s, G, A, boxes, pslot, partial);
 }
 

@@ -54,7 +54,7 @@ class lb_params(ctypes.Structure):
         ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32),
         ("fp16_exponent", ctypes.c_int32), ("variant", ctypes.c_int32),
         ("collision", ctypes.c_int32), ("tau_bulk", ctypes.POINTER(ctypes.c_double)),
-        ("ghost_rate", ctypes.c_double),
+        ("ghost_rate", ctypes.c_double), ("kT", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -135,7 +135,8 @@ def _stream_handle():
 
 
 def make_params(shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_force=False, max_points=0,
-                tile=None, fp16_exponent=0, variant=0, collision="projected", tau_bulk=None, ghost_rate=2.0):
+                tile=None, fp16_exponent=0, variant=0, collision="projected", tau_bulk=None, ghost_rate=2.0, kT=0.0,
+                seed=0):
     """lb_params for boxes of shape (nz, ny, nx); tau and tau_bulk are scalars or per-box sequences."""
     nz, ny, nx = shape
     taus = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, dtype=np.float64), (nboxes,)))
@@ -153,6 +154,8 @@ def make_params(shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_for
     p.variant = variant
     p.collision = COLLISION[collision] if isinstance(collision, str) else int(collision)
     p.ghost_rate = ghost_rate
+    p.kT = kT
+    p.seed = seed
     p._taus = taus  # keep alive
     if tau_bulk is not None:
         tb = np.ascontiguousarray(np.broadcast_to(np.asarray(tau_bulk, dtype=np.float64), (nboxes,)))
@@ -216,13 +219,13 @@ class Lattice:
 
     def __init__(self, shape, storage="fp32", nboxes=1, tau=0.5, rho0=1.0, zero_net_force=False, max_points=0,
                  tile=None, fp16_exponent=0, variant=0, stream=None, collision="projected", tau_bulk=None,
-                 ghost_rate=2.0):
+                 ghost_rate=2.0, kT=0.0, seed=0):
         import torch
         self.torch = torch
         self.shape = tuple(shape)
         self.nboxes = nboxes
         self.params = make_params(shape, storage, nboxes, tau, rho0, zero_net_force, max_points, tile,
-                                  fp16_exponent, variant, collision, tau_bulk, ghost_rate)
+                                  fp16_exponent, variant, collision, tau_bulk, ghost_rate, kT, seed)
         nbytes = lb_workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()

@@ -58,6 +58,7 @@ def test_workspace_bytes_pure_and_monotone():
     dict(storage="mom32", tile=(16, 8, 2)), dict(collision=3), dict(collision=-1),
     dict(collision="mrt", ghost_rate=0.0), dict(collision="mrt", ghost_rate=4.5),
     dict(storage="mom32", collision="bgk"), dict(storage="mom32", collision="mrt", ghost_rate=1.5),
+    dict(kT=-1e-5), dict(kT=float("inf")), dict(storage="mom32", kT=1e-5),
 ])
 def test_bad_params_rejected(kw):
     args = dict(shape=(16, 16, 16), storage="fp32")
