@@ -44,6 +44,8 @@ WORKLOADS = {
     "singularities128_fp16_bgk": ((128, 128, 128), "fp16", 0.5, "singularities", 64),
     "singularities128_thermal": ((128, 128, 128), "fp32", 0.5, "singularities", 64),
     "colloids256_thermal": ((256, 256, 256), "fp32", 0.5, "colloids", 10000),
+    "droplets256": ((256, 256, 256), "fp32", 0.8, "droplets", 64),
+    "chains256": ((256, 256, 256), "fp32", 0.8, "chains", 2048),
 }
 # lattice options of a workload: collision operator (default: the projected operator of
 # Eq. fiexp) and thermal noise
@@ -61,6 +63,10 @@ DESCR = {
                 "(F=-1e-6 z, a=0.117), spread + interpolate + advect every step, counter-force on",
     "boxes": "%d independent %d^3 boxes in one context, %s storage, tau_b ~ U[0.6,1.5], 1-8 fixed colloids "
              "per box (%d total), counter-force on, interpolated velocity accumulated every step",
+    "droplets": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=0.8, %d triangulated droplet interfaces "
+                "(R=12, 642 markers each, tension 1e-4): marker forces, spread, interpolate, move every step",
+    "chains": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=0.8, %d bead-spring chains of 32 markers "
+              "(k=1e-3, l0=1, F_ext=-1e-6 z), counter-force on: marker forces, spread, interpolate, move every step",
 }
 
 
@@ -82,6 +88,13 @@ def make_inputs(kind, shape, n):
         w = workloads.singularities(L=L, n=n)
         pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
         return pos, frc, "static", None
+    if kind == "droplets":
+        pos, tri = workloads.droplets(L, n, radius=12.0, levels=3)
+        return dict(pos=pos, tri=tri, tension=1e-4), None, "droplets", None
+    if kind == "chains":
+        pos = workloads.chains(L, n, 32)
+        ext = np.tile([0.0, 0.0, -1e-6], (len(pos), 1))
+        return dict(pos=pos, ext=ext, chain_len=32, k=1e-3, l0=1.0), None, "chains", None
     pos, frc = workloads.colloids(L, n)
     return pos, frc, "colloid", dict(inv_a=1 / 0.117, inv_aL=0.77)
 
@@ -108,6 +121,17 @@ def build_lattice(shape, storage, tau, kind, pos, frc, model, opts=None):
                              lbm.PointModel(vel_sum=vsum))
         return lat, p
     tile, variant = tuned(shape, storage)
+    if kind in ("droplets", "chains"):
+        w = pos
+        lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "chains"), max_points=len(w["pos"]),
+                          tile=tile, variant=variant, **opts)
+        p = torch.tensor(w["pos"], dtype=torch.float64, device="cuda")
+        if kind == "droplets":
+            lat.add_surface(p, w["tri"], w["tension"])
+        else:
+            lat.add_chains(p, w["chain_len"], w["k"], w["l0"],
+                           ext=torch.tensor(w["ext"], dtype=torch.float64, device="cuda"))
+        return lat, p
     lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "colloid"), max_points=len(pos), tile=tile,
                       variant=variant, **opts)
     p = torch.tensor(pos, dtype=torch.float64, device="cuda")
@@ -191,13 +215,13 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
         lat.close()
     kavg_s = ktot_ms / nlaunch / 1e3
     achieved = BYTES_PER_NODE[storage] * N / kavg_s / 1e9
-    npts = len(pos["pos"]) if kind == "boxes" else len(pos)
+    npts = len(pos["pos"]) if kind in ("boxes", "droplets", "chains") else len(pos)
     r = dict(mlups=N * steps / elapsed / 1e6, ms_per_step=elapsed / steps * 1e3, kernel_ms=kavg_s * 1e3,
              achieved_GBs=achieved, frac=achieved / PEAK_HBM_GBS, nodes=N, points=int(npts), storage=storage,
              launches_timed=nlaunch, steps=steps)
     if kind in ("colloid", "colloids"):
         r["colloid_updates_per_s"] = n * steps / elapsed
-    if kind == "boxes":
+    if kind in ("boxes", "droplets", "chains"):
         r["point_updates_per_s"] = npts * steps / elapsed
     return r, (shape, storage, tau, kind, n, pos, frc, fkind, model)
 
@@ -264,7 +288,7 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32", "mom32": "f32"}[storage],
         "data": "synthetic",
         "config": {"workload": describe(a.workload, r), "nodes": r["nodes"], "points": r["points"],
-                   "seed": 20261200 + {"singularities": 2, "colloids": 3, "boxes": 4}[kind],
+                   "seed": 20261200 + {"singularities": 2, "colloids": 3, "boxes": 4, "droplets": 5, "chains": 6}[kind],
                    "tile": list(tile or ()), "variant": variant},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r["frac"], 4), "traffic": traffic,
@@ -275,7 +299,7 @@ def main():
     if "colloid_updates_per_s" in r:
         out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)
 
-    if not a.no_cpu and kind != "boxes" and a.workload not in OPTS:
+    if not a.no_cpu and kind in ("singularities", "colloids") and a.workload not in OPTS:
         box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
         out["cpu_baseline"] = cb
         # same number of steps on a fresh GPU lattice: error of this storage against the oracle
@@ -299,7 +323,8 @@ def main():
                                  ("colloids512_mom32", 100, False), ("boxes512x32_mom32", 300, False),
                                  ("singularities128_bgk", 2000, False), ("singularities128_mrt", 2000, False),
                                  ("singularities128_fp16_bgk", 2000, False), ("singularities128_thermal", 2000, False),
-                                 ("colloids256_thermal", 300, False)):
+                                 ("colloids256_thermal", 300, False), ("droplets256", 300, False),
+                                 ("chains256", 300, False)):
             rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
             rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
             extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)

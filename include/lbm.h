@@ -191,6 +191,52 @@ int lb_set_equilibrium(lb_ctx* ctx, const double* d_rho, const double* d_u);
 int lb_add_point_forces(lb_ctx* ctx, int64_t n, const double* d_pos, const double* d_force,
                         const int32_t* d_box, int kind, const lb_point_model* model);
 
+/*
+ * Singular forces on curves and surfaces (Sec. I; Eq. singularF with a line or
+ * area measure), carried by markers that move with the fluid.  The library
+ * computes each marker's force from the set's configuration at every step,
+ * writes it to d_force, spreads it like a point force (Sec. III), interpolates
+ * the velocity U at the marker (Sec. IV) and moves the marker by R <- R + U
+ * (no point-particle mobility terms, no thermal displacement).
+ *
+ * LB_ELASTIC_CHAIN: markers form consecutive chains of chain_len (>= 2, n a
+ *   multiple of it); markers i and i+1 of one chain are joined by a Hookean
+ *   spring, force k_spring (|d| - l0) d/|d| on i and its opposite on i+1,
+ *   d = R_{i+1} - R_i taken as the nearest periodic image.
+ * LB_ELASTIC_SURFACE: a closed triangulated surface of tension `tension`;
+ *   vertex force -tension dA/dR_v, where for a triangle (a, b, c) ordered
+ *   counter-clockwise about its unit normal n, dA/da = n x (c - b) / 2.
+ *   d_tri (ntri,3) vertex indices; the incidence d_vt_off (n+1) / d_vt_idx
+ *   (3 ntri) lists, per vertex, the triangles containing it (CSR, ascending).
+ * Both: optional external force per marker d_ext (n,3) added to the elastic
+ * force; d_box (n) the box of each marker or NULL (box 0), one set in one box.
+ * Arrays are FP64 / int32 device arrays owned by the caller and must stay valid
+ * while the set is registered; d_pos is updated in place, d_force overwritten.
+ * Errors: LB_ERR_ARG (bad kind, sizes, NULL arrays, non-finite parameters),
+ * LB_ERR_CAPACITY (markers beyond max_points together with the other sets).
+ */
+#define LB_ELASTIC_CHAIN 0
+#define LB_ELASTIC_SURFACE 1
+
+typedef struct lb_elastic {
+    int32_t kind;            /* LB_ELASTIC_CHAIN or LB_ELASTIC_SURFACE */
+    int32_t chain_len;       /* chain: markers per chain */
+    int64_t n;               /* markers */
+    double* d_pos;           /* (n,3) positions, advanced in place */
+    double* d_force;         /* (n,3) written each step with the marker forces */
+    const double* d_ext;     /* (n,3) external forces or NULL */
+    const int32_t* d_box;    /* (n) box ids or NULL */
+    double* d_vel_out;       /* (n,3) interpolated velocity of the last step, or NULL */
+    double k_spring, l0;     /* chain */
+    double tension;          /* surface */
+    int64_t ntri;            /* surface */
+    const int32_t* d_tri;    /* surface: (ntri,3) */
+    const int32_t* d_vt_off; /* surface: (n+1) */
+    const int32_t* d_vt_idx; /* surface: (3 ntri) */
+} lb_elastic;
+
+int lb_add_elastic(lb_ctx* ctx, const lb_elastic* set);
+
 /* Drop every registered set. */
 int lb_clear_forces(lb_ctx* ctx);
 

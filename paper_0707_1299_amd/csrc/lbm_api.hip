@@ -162,6 +162,9 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     return LB_OK;
 }
 
+// set kind of marker sets (curves and surfaces); the public kinds are 0..2
+constexpr int KIND_ELASTIC = 100;
+
 struct Set {
     long long n;
     const double* pos;
@@ -170,6 +173,7 @@ struct Set {
     int kind;
     lb_point_model model;
     bool has_model;
+    lb_elastic el;   // KIND_ELASTIC only
 };
 
 struct GraphEntry {
@@ -288,11 +292,35 @@ void box_update(lb_ctx* c, hipStream_t s, bool fp16_exp)
     if (sums) c->gc_valid = true;
 }
 
+// marker forces of the curve and surface sets from their current configuration
+void elastic_forces(lb_ctx* c, hipStream_t s)
+{
+    const Geom& G = c->P.G;
+    for (auto& st : c->sets)
+        if (st.kind == KIND_ELASTIC) {
+            ElasticLaunch e;
+            e.kind = st.el.kind;
+            e.chain_len = st.el.chain_len;
+            e.n = st.n;
+            e.pos = st.pos;
+            e.ext = st.el.d_ext;
+            e.frc = st.el.d_force;
+            e.k_spring = st.el.k_spring;
+            e.l0 = st.el.l0;
+            e.tension = st.el.tension;
+            e.tri = st.el.d_tri;
+            e.vt_off = st.el.d_vt_off;
+            e.vt_idx = st.el.d_vt_idx;
+            launch_elastic_forces(G, e, s);
+        }
+}
+
 // one step on stream s; flips c->cur
 void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
 {
     const Geom& G = c->P.G;
     const long long npts = total_points(c);
+    elastic_forces(c, s);
     if (npts > 0 && rebuild) build_points(c, s);
     box_update(c, s, true);
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -315,7 +343,7 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
                    s, e0, e1);
     long long off = 0;
     for (auto& st : c->sets) {
-        const bool adv = st.kind == LB_COLLOIDS;
+        const bool adv = st.kind == LB_COLLOIDS || st.kind == KIND_ELASTIC;
         const bool outs = st.has_model && (st.model.d_vel_out || st.model.d_vel_sum);
         if (adv || outs) {
             AdvectLaunch a;
@@ -326,7 +354,8 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
             a.pos = (double*)st.pos;
             a.boxid = st.box;
             a.advect = adv ? 1 : 0;
-            a.tin = adv ? tin : nullptr;
+            a.tin = st.kind == LB_COLLOIDS ? tin : nullptr;   // markers of curves and surfaces: no zeta'
+
             if (st.has_model) {
                 a.vel_out = st.model.d_vel_out;
                 a.vel_sum = st.model.d_vel_sum;
@@ -544,6 +573,42 @@ int lb_add_point_forces(lb_ctx* c, int64_t n, const double* d_pos, const double*
     return LB_OK;
 }
 
+int lb_add_elastic(lb_ctx* c, const lb_elastic* e)
+{
+    if (!c) return LB_ERR_ARG;
+    if (!e) return fail(c, LB_ERR_ARG, "lb_add_elastic: set is NULL");
+    if (e->kind != LB_ELASTIC_CHAIN && e->kind != LB_ELASTIC_SURFACE) return fail(c, LB_ERR_ARG, "unknown elastic kind");
+    if (e->n <= 0 || !e->d_pos || !e->d_force) return fail(c, LB_ERR_ARG, "elastic set: n <= 0 or NULL arrays");
+    if (e->kind == LB_ELASTIC_CHAIN) {
+        if (e->chain_len < 2 || e->n % e->chain_len != 0)
+            return fail(c, LB_ERR_ARG, "chain: chain_len >= 2 and n a multiple of it");
+        if (!isfinite(e->k_spring) || !isfinite(e->l0) || e->l0 < 0.0)
+            return fail(c, LB_ERR_ARG, "chain: finite k_spring and l0 >= 0");
+    } else {
+        if (e->ntri <= 0 || !e->d_tri || !e->d_vt_off || !e->d_vt_idx)
+            return fail(c, LB_ERR_ARG, "surface: ntri > 0 and the triangle and incidence arrays");
+        if (!isfinite(e->tension)) return fail(c, LB_ERR_ARG, "surface: finite tension");
+        if (e->n > INT32_MAX) return fail(c, LB_ERR_ARG, "surface: too many vertices");
+    }
+    if ((int)c->sets.size() >= LB_MAX_SETS) return fail(c, LB_ERR_CAPACITY, "too many sets");
+    if (total_points(c) + e->n > c->P.cap) return fail(c, LB_ERR_CAPACITY, "more points than max_points");
+    Set s;
+    s.n = e->n;
+    s.pos = e->d_pos;
+    s.frc = e->d_force;
+    s.box = (const int*)e->d_box;
+    s.kind = KIND_ELASTIC;
+    memset(&s.model, 0, sizeof(s.model));
+    s.model.d_vel_out = e->d_vel_out;
+    s.has_model = true;   // inv_a = inv_aL = 0: the markers move with U alone
+    s.el = *e;
+    c->sets.push_back(s);
+    c->gen++;
+    c->bins_valid = false;
+    c->gc_valid = false;
+    return LB_OK;
+}
+
 int lb_clear_forces(lb_ctx* c)
 {
     if (!c) return LB_ERR_ARG;
@@ -572,7 +637,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
         c->steps++;
         left--;
     }
-    const bool moving = has_kind(c, LB_COLLOIDS);
+    const bool moving = has_kind(c, LB_COLLOIDS) || has_kind(c, KIND_ELASTIC);
     const bool pts = total_points(c) > 0;
     if (left > 0 && pts && !moving && !c->bins_valid) {
         build_points(c, c->stream);
@@ -599,8 +664,9 @@ int lb_step(lb_ctx* c, int32_t nsteps)
 static int prepare_fields(lb_ctx* c)
 {
     if (total_points(c) > 0) {
+        elastic_forces(c, c->stream);
         build_points(c, c->stream);
-        if (!has_kind(c, LB_COLLOIDS)) c->bins_valid = true;
+        if (!has_kind(c, LB_COLLOIDS) && !has_kind(c, KIND_ELASTIC)) c->bins_valid = true;
     }
     box_update(c, c->stream, false);
     return LB_OK;

@@ -25,7 +25,22 @@ struct AdvectLaunch {
     const unsigned long long* tin;   // thermal runs: step counter of this step (else NULL)
 };
 
+// marker forces of a chain (kind 0) or surface (kind 1) set
+struct ElasticLaunch {
+    int kind;
+    int chain_len;
+    long long n;
+    const double* pos;
+    const double* ext;
+    double* frc;
+    double k_spring, l0, tension;
+    const int* tri;
+    const int* vt_off;
+    const int* vt_idx;
+};
+
 bool tile_supported(int tx, int ty, int tz);
+void launch_elastic_forces(const Geom& G, const ElasticLaunch& e, hipStream_t s);
 bool launch_lattice(int storage, const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
                     const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
                     const unsigned long long* tin, unsigned long long* tout, hipStream_t s, hipEvent_t ev0 = nullptr,

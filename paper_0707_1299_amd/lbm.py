@@ -67,6 +67,33 @@ class lb_point_model(ctypes.Structure):
     ]
 
 
+LB_ELASTIC_CHAIN = 0
+LB_ELASTIC_SURFACE = 1
+
+
+class lb_elastic(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("chain_len", ctypes.c_int32), ("n", ctypes.c_int64),
+        ("d_pos", ctypes.c_void_p), ("d_force", ctypes.c_void_p), ("d_ext", ctypes.c_void_p),
+        ("d_box", ctypes.c_void_p), ("d_vel_out", ctypes.c_void_p),
+        ("k_spring", ctypes.c_double), ("l0", ctypes.c_double), ("tension", ctypes.c_double),
+        ("ntri", ctypes.c_int64), ("d_tri", ctypes.c_void_p), ("d_vt_off", ctypes.c_void_p),
+        ("d_vt_idx", ctypes.c_void_p),
+    ]
+
+
+def vertex_triangle_incidence(tri, nverts):
+    """CSR lists of the triangles containing each vertex, ascending (host side)."""
+    tri = np.asarray(tri, dtype=np.int64).reshape(-1, 3)
+    t = np.repeat(np.arange(len(tri)), 3)
+    v = tri.ravel()
+    order = np.lexsort((t, v))
+    counts = np.bincount(v, minlength=nverts)
+    off = np.zeros(nverts + 1, dtype=np.int32)
+    off[1:] = np.cumsum(counts)
+    return off, t[order].astype(np.int32)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("liblbm.so is not built (%s); run python -m paper_0707_1299_amd.build" % LIB_PATH)
@@ -84,6 +111,7 @@ def _load():
         "lb_set_equilibrium": (ctypes.c_int, [vp, vp, vp]),
         "lb_add_point_forces": (ctypes.c_int, [vp, i64, vp, vp, vp, ctypes.c_int, P(lb_point_model)]),
         "lb_clear_forces": (ctypes.c_int, [vp]),
+        "lb_add_elastic": (ctypes.c_int, [vp, P(lb_elastic)]),
         "lb_step": (ctypes.c_int, [vp, i32]),
         "lb_moments": (ctypes.c_int, [vp, vp, vp]),
         "lb_interp_velocity": (ctypes.c_int, [vp, i64, vp, vp, vp]),
@@ -264,6 +292,35 @@ class Lattice:
         m = None if model is None else ctypes.byref(model.to_c())
         self._check(_L.lb_add_point_forces(self.ctx, n, _ptr(pos), _ptr(force), _ptr(box), kind, m))
         self._keep += [pos, force, box, model]
+
+    def add_chains(self, pos, chain_len, k_spring, l0, ext=None, box=None, vel_out=None):
+        """Bead-spring chains of chain_len consecutive markers; pos torch float64 (n,3), moved in place.
+        Returns the (n,3) tensor the library writes the marker forces into."""
+        e = lb_elastic()
+        e.kind, e.chain_len, e.n = LB_ELASTIC_CHAIN, chain_len, pos.shape[0]
+        e.k_spring, e.l0 = k_spring, l0
+        return self._add_elastic(e, pos, ext, box, vel_out, [])
+
+    def add_surface(self, pos, tri, tension, ext=None, box=None, vel_out=None):
+        """Closed triangulated surface (tri (ntri,3), counter-clockwise about the outward normal) of
+        the given tension; pos torch float64 (n,3), moved in place.  Returns the marker-force tensor."""
+        t = self.torch
+        tri_np = np.asarray(tri, dtype=np.int32).reshape(-1, 3)
+        off, idx = vertex_triangle_incidence(tri_np, pos.shape[0])
+        d_tri = t.tensor(tri_np, device="cuda")
+        d_off = t.tensor(off, device="cuda")
+        d_idx = t.tensor(idx, device="cuda")
+        e = lb_elastic()
+        e.kind, e.n, e.tension, e.ntri = LB_ELASTIC_SURFACE, pos.shape[0], tension, len(tri_np)
+        e.d_tri, e.d_vt_off, e.d_vt_idx = _ptr(d_tri), _ptr(d_off), _ptr(d_idx)
+        return self._add_elastic(e, pos, ext, box, vel_out, [d_tri, d_off, d_idx])
+
+    def _add_elastic(self, e, pos, ext, box, vel_out, keep):
+        frc = self.torch.zeros_like(pos)
+        e.d_pos, e.d_force, e.d_ext, e.d_box, e.d_vel_out = _ptr(pos), _ptr(frc), _ptr(ext), _ptr(box), _ptr(vel_out)
+        self._check(_L.lb_add_elastic(self.ctx, ctypes.byref(e)))
+        self._keep += [pos, frc, ext, box, vel_out] + keep
+        return frc
 
     def clear_forces(self):
         self._check(_L.lb_clear_forces(self.ctx))

@@ -15,6 +15,11 @@ oracle receive exactly these arrays.  Seeds are 20261200 + workload index.
   mobility_boxes   per box 1..8 fixed colloids at the first k sites of the
                    2x2x2 sub-lattice of spacing L/2, sub-node offsets
                    U[0, 1)^3, tau_b ~ U[0.6, 1.5]
+  droplets         n spherical interfaces (geodesic triangulations of the
+                   icosahedron) of radius r on a cubic grid with uniform
+                   jitter of the centres
+  chains           n random-walk chains of m markers, bond length b,
+                   starts uniform
 """
 from __future__ import annotations
 
@@ -77,3 +82,59 @@ def mobility_boxes(nboxes: int = 512, L: int = 32, index: int = 4, fz: float = -
     force = np.tile([0.0, 0.0, fz], (len(pos), 1))
     return dict(pos=pos, force=force, box=np.array(box, dtype=np.int32), offsets=np.array(off),
                 counts=counts, taus=taus)
+
+
+def geodesic_sphere(levels: int):
+    """Unit-sphere triangulation: an icosahedron subdivided `levels` times, vertices projected to
+    the sphere, triangles counter-clockwise seen from outside (geometry only)."""
+    t = (1 + 5 ** 0.5) / 2
+    verts = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in
+             ((-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+              (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1))]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+             (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(levels):
+        mids = {}
+
+        def mid(i, j):
+            k = (min(i, j), max(i, j))
+            if k not in mids:
+                m = verts[i] + verts[j]
+                verts.append(m / np.linalg.norm(m))
+                mids[k] = len(verts) - 1
+            return mids[k]
+
+        faces = [f for a, b, c in faces for f in ((a, mid(a, b), mid(c, a)), (b, mid(b, c), mid(a, b)),
+                                                   (c, mid(c, a), mid(b, c)), (mid(a, b), mid(b, c), mid(c, a)))]
+    V = np.array(verts)
+    F = np.array(faces, dtype=np.int32)
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    flip = (n * V[F].mean(1)).sum(1) < 0
+    F[flip] = F[flip][:, [0, 2, 1]]
+    return V, F
+
+
+def droplets(L: int, n: int, radius: float, levels: int = 3, index: int = 5):
+    """n spheres of the given radius on the sites of a cubic grid filling the box, centres jittered
+    by U[-1/2, 1/2)^3; returns (positions, triangles) of one combined marker set."""
+    g = rng(index)
+    k = int(np.ceil(n ** (1 / 3)))
+    sp = L / k
+    V, F = geodesic_sphere(levels)
+    pos, tri = [], []
+    for j in range(n):
+        site = np.array([j % k, (j // k) % k, j // (k * k)], dtype=np.float64)
+        c = (site + 0.5) * sp + g.uniform(-0.5, 0.5, 3)
+        pos.append(c + radius * V)
+        tri.append(F + j * len(V))
+    return np.concatenate(pos), np.concatenate(tri)
+
+
+def chains(L: int, n: int, m: int, bond: float = 1.0, index: int = 6):
+    """n chains of m markers: uniform starts, steps of length `bond` in uniform directions."""
+    g = rng(index)
+    start = g.uniform(0, L, (n, 1, 3))
+    steps = _unit(g, n * (m - 1)).reshape(n, m - 1, 3) * bond
+    pos = np.concatenate([start, start + np.cumsum(steps, axis=1)], axis=1).reshape(-1, 3)
+    return pos - L * np.floor(pos / L)
