@@ -47,7 +47,8 @@ int max_axis_tiles(int n, int t)
 }
 
 struct Layout {
-    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, pslot, partial, fpart, pmax, tmax, ticket, tctr, err,
+    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, tlist_tmp, pslot, partial, fpart, pmax, tmax, ticket, tctr,
+        err,
         diag, diagout;
     size_t total;
 };
@@ -148,6 +149,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.toff = take(sizeof(int) * (G.ntiles + 1));
     L.bsum = take(sizeof(int) * scan_blocks(G.ntiles));
     L.tlist = take(sizeof(int) * P.cap * G.maxp);
+    L.tlist_tmp = take(sizeof(int) * P.cap * G.maxp);
     L.pslot = take(sizeof(int) * P.cap * G.maxp);
     L.partial = take(sizeof(double) * 3 * P.cap * G.maxp);
     L.fpart = take(sizeof(double) * 3 * p->nboxes * P.chunks);
@@ -215,6 +217,7 @@ struct lb_ctx {
     int* toff() const { return (int*)(ws + P.L.toff); }
     int* bsum() const { return (int*)(ws + P.L.bsum); }
     int* tlist() const { return (int*)(ws + P.L.tlist); }
+    int* tlist_tmp() const { return (int*)(ws + P.L.tlist_tmp); }
     int* pslot() const { return (int*)(ws + P.L.pslot); }
     double* partial() const { return (double*)(ws + P.L.partial); }
     double* fpart() const { return (double*)(ws + P.L.fpart); }
@@ -275,7 +278,7 @@ void build_points(lb_ctx* c, hipStream_t s)
         off += st.n;
     }
     launch_bins(c->p.storage, G, off, c->rec(), c->count(), c->bsum(), c->toff(), c->cursor(), c->tlist(),
-                c->pslot(), s);
+                c->tlist_tmp(), c->pslot(), s);
     c->gc_valid = false;
 }
 

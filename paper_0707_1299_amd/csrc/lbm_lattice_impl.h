@@ -33,7 +33,6 @@ namespace lbm {
 
 enum Mode { M_STEP = 0, M_MOMENTS = 1, M_DIAG = 2 };
 
-constexpr int CHUNK = 32;  // points reduced per LDS round in the interpolation
 
 template <bool NT, class S> __device__ __forceinline__ S ld(const S* p)
 {
@@ -338,35 +337,37 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     }
 
     // ---- interpolation partial sums: sum over this tile's nodes of u * deltaP(x - R)
+    // u of the tile's nodes goes to LDS; wave w then takes the tile's points w, w + 4, ...,
+    // lane l standing for stencil node (l & 3, (l >> 2) & 3, l >> 4) of the point, and one
+    // wave reduction per component gives the point's partial.
     if (k1 > k0) {
-        __shared__ T red[4][CHUNK][3];
-        for (int c0 = k0; c0 < k1; c0 += CHUNK) {
-            const int cn = min(CHUNK, k1 - c0);
-            for (int kk = 0; kk < cn; ++kk) {
-                const PRec<T>& r = rec[pk_point(tlist[c0 + kk])];
-                T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
-                      stencil_w<T>(z, r.bz, G.nz, r.wz);
-                if (!valid) w = T(0);
-                T sx = 0, sy = 0, sz = 0;
-                if (__any(w != T(0))) {
-                    sx = wave_sum(ux * w);
-                    sy = wave_sum(uy * w);
-                    sz = wave_sum(uz * w);
-                }
-                if (lane == 0) {
-                    red[wave][kk][0] = sx;
-                    red[wave][kk][1] = sy;
-                    red[wave][kk][2] = sz;
-                }
+        __shared__ T su[3][BLOCK];
+        su[0][threadIdx.x] = valid ? ux : T(0);
+        su[1][threadIdx.x] = valid ? uy : T(0);
+        su[2][threadIdx.x] = valid ? uz : T(0);
+        __syncthreads();
+        const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
+        const int x0 = itx * TX, y0 = ity * TY, z0 = itz * TZ;
+        for (int kk = k0 + wave; kk < k1; kk += BLOCK / 64) {
+            const PRec<T>& r = rec[pk_point(tlist[kk])];
+            int gx = r.bx + dx, gy = r.by + dy, gz = r.bz + dz;
+            if (gx >= G.nx) gx -= G.nx;
+            if (gy >= G.ny) gy -= G.ny;
+            if (gz >= G.nz) gz -= G.nz;
+            const int lx2 = gx - x0, ly2 = gy - y0, lz2 = gz - z0;
+            const bool in = unsigned(lx2) < unsigned(TX) && unsigned(ly2) < unsigned(TY) && unsigned(lz2) < unsigned(TZ);
+            const int li = in ? lx2 + TX * (ly2 + TY * lz2) : 0;
+            const T w = in ? r.wx[dx] * r.wy[dy] * r.wz[dz] : T(0);
+            const T sx = wave_sum(su[0][li] * w);
+            const T sy = wave_sum(su[1][li] * w);
+            const T sz = wave_sum(su[2][li] * w);
+            if (lane == 0) {
+                out0[(long long)kk * 3 + 0] = double(sx);
+                out0[(long long)kk * 3 + 1] = double(sy);
+                out0[(long long)kk * 3 + 2] = double(sz);
             }
-            __syncthreads();
-            if (threadIdx.x < 3 * cn) {
-                const int kk = threadIdx.x / 3, c = threadIdx.x % 3;
-                out0[(long long)(c0 + kk) * 3 + c] =
-                    ((double(red[0][kk][c]) + double(red[1][kk][c])) + double(red[2][kk][c])) + double(red[3][kk][c]);
-            }
-            __syncthreads();
         }
+        __syncthreads();   // su is rewritten by the block's next tile
     }
 }
 

@@ -197,25 +197,23 @@ __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, cons
 
 // 4. sort every tile's list by point index (so sums run in a fixed order) and
 //    record, for each point and each tile it touches, where it sits in that
-//    tile's list.
-__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const int* __restrict__ toff, int* __restrict__ tlist,
+//    tile's list.  One wave per tile: each entry's position is the number of
+//    smaller entries in the same list (entries are distinct), so a crowded
+//    tile costs k^2 / 64 compares per lane instead of a serial k^2 sort.
+__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const int* __restrict__ toff,
+                                                    const int* __restrict__ tin, int* __restrict__ tout,
                                                     int* __restrict__ pslot)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= G.ntiles) return;
+    const int lane = threadIdx.x & 63;
     const int a = toff[t], b = toff[t + 1];
-    for (int i = a + 1; i < b; ++i) {
-        const int v = tlist[i];
-        int j = i - 1;
-        while (j >= a && tlist[j] > v) {
-            tlist[j + 1] = tlist[j];
-            --j;
-        }
-        tlist[j + 1] = v;
-    }
-    for (int i = a; i < b; ++i) {
-        const int e = tlist[i];
-        pslot[(long long)pk_point(e) * G.maxp + pk_slot(e)] = i;
+    for (int i = a + lane; i < b; i += 64) {
+        const int v = tin[i];
+        int rank = 0;
+        for (int j = a; j < b; ++j) rank += tin[j] < v ? 1 : 0;
+        tout[a + rank] = v;
+        pslot[(long long)pk_point(v) * G.maxp + pk_slot(v)] = a + rank;
     }
 }
 
@@ -553,23 +551,20 @@ void launch_prep(int storage, const Geom& G, long long n, long long off, const d
 long long scan_blocks(long long ntiles) { return (ntiles + SCAN_B - 1) / SCAN_B; }
 
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
-                 int* cursor, int* tlist, int* pslot, hipStream_t s)
+                 int* cursor, int* tlist, int* tlist_tmp, int* pslot, hipStream_t s)
 {
     const unsigned nb = (unsigned)scan_blocks(G.ntiles);
     hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, (const int*)count, bsum);
     hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, count, (const int*)bsum, toff, cursor);
     if (npts <= 0) return;
-    if (storage == ST_FP64) {
+    if (storage == ST_FP64)
         hipLaunchKernelGGL(k_fill<double>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts,
-                           (const PRec<double>*)rec, (const int*)toff, cursor, tlist);
-        hipLaunchKernelGGL(k_sort_slots, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G, (const int*)toff, tlist,
-                           pslot);
-    } else {
+                           (const PRec<double>*)rec, (const int*)toff, cursor, tlist_tmp);
+    else
         hipLaunchKernelGGL(k_fill<float>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts, (const PRec<float>*)rec,
-                           (const int*)toff, cursor, tlist);
-        hipLaunchKernelGGL(k_sort_slots, dim3(nblk(G.ntiles, 256)), dim3(256), 0, s, G, (const int*)toff, tlist,
-                           pslot);
-    }
+                           (const int*)toff, cursor, tlist_tmp);
+    hipLaunchKernelGGL(k_sort_slots, dim3(nblk(G.ntiles, 4)), dim3(256), 0, s, G, (const int*)toff,
+                       (const int*)tlist_tmp, tlist, pslot);
 }
 
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
