@@ -5,7 +5,8 @@
 // mix the high halves of the products with the other counter words and the
 // key, and advance the key by 0x9E3779B9, 0xBB67AE85 between rounds.
 // Normals: Box-Muller on pairs of 32-bit outputs, u = (x + 1/2) 2^-32,
-// z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = sqrt(-2 ln u0) sin(2 pi u1).
+// z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = sqrt(-2 ln u0) sin(2 pi u1)
+// (FP64 with the library functions, FP32 with the hardware instructions).
 //
 // Modes: the fifteen non-conserved D3Q19 polynomials of the orthogonal basis
 // of Duenweg, Schiller and Ladd (2007), mutually w-orthogonal and orthogonal
@@ -45,6 +46,18 @@ template <class T> __device__ __forceinline__ void box_muller(uint32_t a, uint32
     const T t = T(2.0 * 3.14159265358979323846) * u1;
     z0 = r * cos(t);
     z1 = r * sin(t);
+}
+
+// FP32: the hardware transcendentals fit Box-Muller directly: v_log_f32 is log2 and
+// v_sin_f32 / v_cos_f32 take their argument in revolutions, i.e. sin(2 pi u) = v_sin(u)
+// for u in (0, 1), with no range reduction.
+template <> __device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b, float& z0, float& z1)
+{
+    constexpr float two_m32 = 2.3283064365386962890625e-10f;
+    const float u0 = (float(a) + 0.5f) * two_m32, u1 = (float(b) + 0.5f) * two_m32;
+    const float r = __builtin_sqrtf(-2.0f * 0.69314718055994530942f * __builtin_amdgcn_logf(u0));
+    z0 = r * __builtin_amdgcn_cosf(u1);
+    z1 = r * __builtin_amdgcn_sinf(u1);
 }
 
 // The fifteen mode polynomials at velocity i (integers on D3Q19).
