@@ -60,7 +60,8 @@ DESCR = {
     "singularities": "%d^3 periodic D3Q19 forced MRT, %s deviation storage, tau=1/2, %d seeded point "
                      "singularities (Stokeslet/stresslet/rotlet, |s|<=1e-5) as %d point forces",
     "colloids": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=1/2, %d sedimenting point colloids "
-                "(F=-1e-6 z, a=0.117), spread + interpolate + advect every step, counter-force on",
+                "(F=-1e-6 z, a=0.117 at 256^3, 0.684 at 512^3), spread + interpolate + advect every step, "
+                "counter-force on",
     "boxes": "%d independent %d^3 boxes in one context, %s storage, tau_b ~ U[0.6,1.5], 1-8 fixed colloids "
              "per box (%d total), counter-force on, interpolated velocity accumulated every step",
     "droplets": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=0.8, %d triangulated droplet interfaces "
@@ -96,7 +97,9 @@ def make_inputs(kind, shape, n):
         ext = np.tile([0.0, 0.0, -1e-6], (len(pos), 1))
         return dict(pos=pos, ext=ext, chain_len=32, k=1e-3, l0=1.0), None, "chains", None
     pos, frc = workloads.colloids(L, n)
-    return pos, frc, "colloid", dict(inv_a=1 / 0.117, inv_aL=0.77)
+    # a = 0.117 (Table 1) at 256^3; a = 0.684 (volume fraction ~1e-3 with 10^5 colloids) at 512^3
+    a = 0.684 if L >= 512 else 0.117
+    return pos, frc, "colloid", dict(inv_a=1 / a, inv_aL=0.77)
 
 
 def tuned(shape, storage, nboxes=1):

@@ -1,0 +1,75 @@
+"""Full-size colloid configurations against the FP64 oracle, in the launch
+configuration the benchmark times (tuned tile and access variant, graph
+replay of 2-step chunks):
+
+* 256^3 with 10^4 sedimenting colloids (a = 0.117), FP32 and FP16-scaled
+  storage, 10 steps;
+* 512^3 with 10^5 colloids (a = 0.684), FP32 storage, 3 steps (the oracle
+  holds ~65 GB of FP64 state on the host).
+
+Velocity field, interpolated velocities and positions; bars 1e-5 (FP32) and
+the FP16 rounding bound 5e-3, as in the smaller parity tests.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0707_1299_amd import lbm, tune, workloads  # noqa: E402
+
+TOL = {"fp32": 1e-5, "fp16": 5e-3}
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def run_both(L, n, a, storage, steps):
+    pos, frc = workloads.colloids(L, n)
+    inv_a, inv_aL = 1 / a, 0.77
+    tile, variant = tune.lookup((L, L, L), storage) or (None, 0)
+    lat = lbm.Lattice((L, L, L), storage, tau=0.5, zero_net_force=True, max_points=n, tile=tile, variant=variant)
+    p = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    f = torch.tensor(frc, dtype=torch.float64, device="cuda")
+    vel = torch.zeros_like(p)
+    lat.add_point_forces(p, f, None, lbm.LB_COLLOIDS, lbm.PointModel(vel_out=vel, inv_a=inv_a, inv_aL=inv_aL))
+    lat.step(steps)
+    _, u = lat.moments(rho=False)
+    lat.sync()
+    ug = u[0].cpu().numpy()
+    Rg, Ug = p.cpu().numpy(), vel.cpu().numpy()
+    del u
+    lat.close()
+    print("gpu done (%s, tile %s, variant %d)" % (storage, tile, variant), flush=True)
+    box = oracle.Box((L, L, L), 0.5, 1.0, zero_net_force=True)
+    box.sets = [oracle.ForceSet(pos.copy(), frc.copy(), kind="colloid", inv_a=inv_a, inv_aL=inv_aL)]
+    box.step(steps)
+    _, uo = box.moments()
+    d = np.abs(Rg - box.sets[0].pos)
+    d = np.minimum(d, L - d)
+    disp = np.abs(box.sets[0].pos - pos)
+    disp = np.minimum(disp, L - disp).max()
+    return rel(ug, uo), rel(Ug, box.sets[0].U), d.max() / disp
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_256_cubed_10k_colloids(storage):
+    e, eU, eR = run_both(256, 10000, 0.117, storage, 10)
+    print("256^3 %s: u rel %.3e, U rel %.3e, pos err/disp %.3e" % (storage, e, eU, eR))
+    assert e <= TOL[storage]
+    assert eU <= 10 * TOL[storage]
+    assert eR <= 10 * TOL[storage]
+
+
+def test_512_cubed_100k_colloids_fp32():
+    e, eU, eR = run_both(512, 100000, 0.684, "fp32", 3)
+    print("512^3 fp32: u rel %.3e, U rel %.3e, pos err/disp %.3e" % (e, eU, eR))
+    assert e <= TOL["fp32"]
+    assert eU <= 10 * TOL["fp32"]
+    assert eR <= 10 * TOL["fp32"]

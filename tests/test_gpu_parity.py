@@ -295,12 +295,14 @@ def test_colloid_radius_constraint_rejected():
 
 def test_full_size_128_fp32_bench_configuration():
     """The benchmark workload (128^3, FP32, 64 singularities) against the oracle over 60 steps,
-    in the launch configuration the benchmark uses (default tiles, graph replay)."""
+    in the launch configuration the benchmark uses (tuned tile and variant, graph replay)."""
+    from paper_0707_1299_amd import tune
     L = 128
     w = workloads.singularities(L=L, n=64)
     pos, frc = lbm.lb_expand_multipoles(w["types"], w["centers"], w["axes"], w["e1"], w["strengths"], w["sep"])
     sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
-    lat, u, outs = run_gpu((L, L, L), "fp32", 0.5, sets, 60)
+    tile, variant = tune.lookup((L, L, L), "fp32") or (None, 0)
+    lat, u, outs = run_gpu((L, L, L), "fp32", 0.5, sets, 60, tile=tile, variant=variant)
     box, uo = run_oracle((L, L, L), 0.5, sets, 60)
     e = rel(u[0], uo)
     print("128^3 fp32 rel err %.3e" % e)
