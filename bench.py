@@ -183,10 +183,44 @@ def cpu_baseline(kind, shape, storage, tau, pos, frc, model, budget_s=12.0):
     box.step(steps)
     dt = time.perf_counter() - t0
     N = shape[0] * shape[1] * shape[2]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return box, steps + 1, dict(value=round(N * steps / dt / 1e6, 3), unit="MLUPS", cores=cores, kind="oracle",
+    return box, steps + 1, dict(value=round(N * steps / dt / 1e6, 3), unit="MLUPS", cores=oracle.threads(),
+                                kind="oracle",
                                 sample="steps 2..%d of the same workload (%d steps, %.1f s), FP64, OpenMP"
                                        % (steps + 1, steps, dt))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_rates():
+    """The FP64 oracle on bounded samples of the other configurations, all host threads and one:
+    32^3 Stokeslet, 256^3 with 10^4 colloids, 512^3 with 10^5 colloids (2 steps), and the
+    128^3 singularities box on one thread."""
+    import oracle
+    from paper_0707_1299_amd import workloads
+    out = {"cpu": cpu_model(), "threads": oracle.threads()}
+    pos, frc = workloads.stokeslet_box(32)
+    _, _, cb = cpu_baseline("static", (32, 32, 32), "fp64", 0.5, pos, frc, None, budget_s=5.0)
+    out["stokeslet32_fp64"] = cb
+    for L, n, budget in ((256, 10000, 10.0), (512, 100000, 1.0)):
+        pos, frc, fkind, model = make_inputs("colloids", (L, L, L), n)
+        _, _, cb = cpu_baseline(fkind, (L, L, L), "fp64", 0.5, pos, frc, model, budget_s=budget)
+        out["colloids%d" % L] = cb
+        print("oracle %d^3 done" % L, file=sys.stderr, flush=True)
+    nthr = oracle.threads()
+    oracle.set_threads(1)
+    pos, frc, fkind, model = make_inputs("singularities", (128, 128, 128), 64)
+    _, _, cb = cpu_baseline(fkind, (128, 128, 128), "fp64", 0.5, pos, frc, model, budget_s=8.0)
+    oracle.set_threads(nthr)
+    out["singularities128_one_thread"] = cb
+    return out
 
 
 def run_workload(name, steps, warmup, timing_steps, mlp=False):
@@ -334,6 +368,8 @@ def main():
                                                      for k, v in rr.items()}
             print("workload %s done" % name, file=sys.stderr, flush=True)
         out["workloads"] = extra
+        if not a.no_cpu:
+            out["oracle_rates"] = oracle_rates()
     print(json.dumps(out))
 
 

@@ -63,6 +63,9 @@ def lib():
         L.orc_advect.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                                       _dp, _dp, _dp, _dp, _dp]
         L.orc_equilibrium.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, _dp, _dp, _dp]
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -72,6 +75,15 @@ def _p(a):
         return None
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_dp)
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 def phi(r: float) -> float:

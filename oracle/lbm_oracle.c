@@ -35,6 +35,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define NQ 19
 
@@ -344,3 +345,7 @@ void orc_equilibrium(int nx, int ny, int nz, double rho0, const double* rho, con
         }
     }
 }
+
+/* Threads the parallel loops use, and a way to set them (for timing the oracle). */
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { omp_set_num_threads(n); }
