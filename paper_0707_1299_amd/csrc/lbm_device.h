@@ -23,6 +23,16 @@ __host__ __device__ constexpr int cvel(int i, int a)
 
 __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// the kernels rely on velocities 2k+1 and 2k+2 being opposite
+constexpr bool opposite_pairs()
+{
+    for (int i = 1; i < NQ; i += 2)
+        for (int a = 0; a < 3; ++a)
+            if (cvel(i + 1, a) != -cvel(i, a)) return false;
+    return true;
+}
+static_assert(opposite_pairs(), "velocity table must list opposite pairs");
+
 enum Storage { ST_FP64 = 0, ST_FP32 = 1, ST_FP16 = 2, ST_MOM32 = 3 };
 
 template <int ST> struct StoreT;

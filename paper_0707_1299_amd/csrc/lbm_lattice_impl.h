@@ -107,19 +107,20 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         pull_node<ST, NTL>(sb, G.sp, pbytes, G.ny, G.nx, x, y, z, xm, xp, ym, yp, zm, zp, f);
     }
 
-    // ---- moments (10 values)
-    T drho = 0, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+    // ---- moments (10 values), over opposite pairs (i, i+1): the pair sum feeds the even
+    // moments (mass, second moments), the difference the odd ones (momentum)
+    T drho = f[0], jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-        const T v = f[i];
+    for (int i = 1; i < NQ; i += 2) {
+        const T sm = f[i] + f[i + 1], df = f[i] - f[i + 1];
         const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-        drho += v;
-        if (cx != 0) { jx += cx > 0 ? v : -v; pxx += v; }
-        if (cy != 0) { jy += cy > 0 ? v : -v; pyy += v; }
-        if (cz != 0) { jz += cz > 0 ? v : -v; pzz += v; }
-        if (cx * cy != 0) pxy += cx * cy > 0 ? v : -v;
-        if (cx * cz != 0) pxz += cx * cz > 0 ? v : -v;
-        if (cy * cz != 0) pyz += cy * cz > 0 ? v : -v;
+        drho += sm;
+        if (cx != 0) { jx += cx > 0 ? df : -df; pxx += sm; }
+        if (cy != 0) { jy += cy > 0 ? df : -df; pyy += sm; }
+        if (cz != 0) { jz += cz > 0 ? df : -df; pzz += sm; }
+        if (cx * cy != 0) pxy += cx * cy > 0 ? sm : -sm;
+        if (cx * cz != 0) pxz += cx * cz > 0 ? sm : -sm;
+        if (cy * cz != 0) pyz += cy * cz > 0 ? sm : -sm;
     }
     if constexpr (ST == ST_FP16) {
         const T s = MODE == M_STEP ? T(B.s_in) : T(ldexpf(1.0f, -B.e_data));
@@ -199,6 +200,30 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const T ax = jx + gx, ay = jy + gy, az = jz + gz;
     const T third = T(1.0 / 3.0);
     const T sxx = pxx - drho * third, syy = pyy - drho * third, szz = pzz - drho * third;
+    T br[NQ];   // post-collision f*_i / w_i
+    if constexpr (COLL && ST != ST_MOM32) {
+        // ghost part of the pulled state (deviation minus its projection onto 1, c, Q),
+        // carried over with factor kappa_g, in units of w_i; taken first so that the pulled
+        // populations are dead before the collision
+        const T kg = T(B.kappa_g);
+        const T hbase = drho - T(1.5) * (sxx + syy + szz);
+        T s_in = T(1);
+        if constexpr (ST == ST_FP16) s_in = T(B.s_in);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+            T a = 0, q = 0;
+            if (cx != 0) { a += cx > 0 ? jx : -jx; q += sxx; }
+            if (cy != 0) { a += cy > 0 ? jy : -jy; q += syy; }
+            if (cz != 0) { a += cz > 0 ? jz : -jz; q += szz; }
+            if (cx * cy != 0) q += cx * cy > 0 ? T(2) * pxy : T(-2) * pxy;
+            if (cx * cz != 0) q += cx * cz > 0 ? T(2) * pxz : T(-2) * pxz;
+            if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
+            const T hb = hbase + T(3) * a + T(4.5) * q;
+            const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
+            br[i] = kg * (f[i] * s_in * inv_w - hb);
+        }
+    }
     const T tau = T(B.tau), om = T(B.omega);
     T Bxx, Byy, Bzz;
     if constexpr (COLL) {
@@ -223,69 +248,52 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
     const T base = drho - T(1.5) * (Bxx + Byy + Bzz);
 
-    T br[NQ];
+    // f*_i / w_i = base + c_i.(3A) + sum_a c_ia^2 (9/2) B_aa + sum_{a<b} c_ia c_ib 9 B_ab: for an
+    // opposite pair the even part is shared and the odd part (3A.c_i) changes sign
+    const T a3x = T(3) * ax, a3y = T(3) * ay, a3z = T(3) * az;
+    const T bxx = T(4.5) * Bxx, byy = T(4.5) * Byy, bzz = T(4.5) * Bzz;
+    const T bxy = T(9) * Bxy, bxz = T(9) * Bxz, byz = T(9) * Byz;
+    constexpr bool GHOST = COLL && ST != ST_MOM32;
+    // with the ghost part already in br: br + (ev +- od), the same sum as (ev +- od) + br
+    br[0] = GHOST ? br[0] + base : base;
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    for (int i = 1; i < NQ; i += 2) {
         const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-        T a = 0, q = 0;
-        if (cx != 0) { a += cx > 0 ? ax : -ax; q += Bxx; }
-        if (cy != 0) { a += cy > 0 ? ay : -ay; q += Byy; }
-        if (cz != 0) { a += cz > 0 ? az : -az; q += Bzz; }
-        if (cx * cy != 0) q += cx * cy > 0 ? T(2) * Bxy : T(-2) * Bxy;
-        if (cx * cz != 0) q += cx * cz > 0 ? T(2) * Bxz : T(-2) * Bxz;
-        if (cy * cz != 0) q += cy * cz > 0 ? T(2) * Byz : T(-2) * Byz;
-        br[i] = base + T(3) * a + T(4.5) * q;
-    }
-    if constexpr (COLL && ST != ST_MOM32) {
-        // ghost part of the pulled state (deviation minus its projection onto 1, c, Q),
-        // carried over with factor kappa_g; added here in units of w_i
-        const T kg = T(B.kappa_g);
-        const T hbase = drho - T(1.5) * (sxx + syy + szz);
-        T s_in = T(1);
-        if constexpr (ST == ST_FP16) s_in = T(B.s_in);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-            T a = 0, q = 0;
-            if (cx != 0) { a += cx > 0 ? jx : -jx; q += sxx; }
-            if (cy != 0) { a += cy > 0 ? jy : -jy; q += syy; }
-            if (cz != 0) { a += cz > 0 ? jz : -jz; q += szz; }
-            if (cx * cy != 0) q += cx * cy > 0 ? T(2) * pxy : T(-2) * pxy;
-            if (cx * cz != 0) q += cx * cz > 0 ? T(2) * pxz : T(-2) * pxz;
-            if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
-            const T hb = hbase + T(3) * a + T(4.5) * q;
-            const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
-            br[i] += kg * (f[i] * s_in * inv_w - hb);
-        }
+        T ev = base, od = 0;
+        if (cx != 0) { od += cx > 0 ? a3x : -a3x; ev += bxx; }
+        if (cy != 0) { od += cy > 0 ? a3y : -a3y; ev += byy; }
+        if (cz != 0) { od += cz > 0 ? a3z : -a3z; ev += bzz; }
+        if (cx * cy != 0) ev += cx * cy > 0 ? bxy : -bxy;
+        if (cx * cz != 0) ev += cx * cz > 0 ? bxz : -bxz;
+        if (cy * cz != 0) ev += cy * cz > 0 ? byz : -byz;
+        br[i] = GHOST ? br[i] + (ev + od) : ev + od;
+        br[i + 1] = GHOST ? br[i + 1] + (ev - od) : ev - od;
     }
     if constexpr (COLL == 2 && ST != ST_MOM32) {
         // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2);
         // added here in units of w_i
         const unsigned long long t = *tin;
         const uint32_t node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
-        T r[16];
+        const T sr = sqrt(rho);
+        // each call gives four normals for modes 4j .. 4j+3, applied at once (few live registers)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const Philox4 q = node_draw(node, uint32_t(box), t, uint32_t(j), G.seed_lo, G.seed_hi);
-            box_muller<T>(q.v[0], q.v[1], r[4 * j], r[4 * j + 1]);
-            box_muller<T>(q.v[2], q.v[3], r[4 * j + 2], r[4 * j + 3]);
-        }
-        const T sr = sqrt(rho);
-        T amp[15];
+            T r[4];
+            box_muller<T>(q.v[0], q.v[1], r[0], r[1]);
+            box_muller<T>(q.v[2], q.v[3], r[2], r[3]);
 #pragma unroll
-        for (int k = 0; k < 15; ++k) {
-            const T nzk = T(k == 0 ? B.nz_b : (k < 6 ? B.nz_s : B.nz_g));
-            amp[k] = sr * nzk * T(1.0 / __builtin_sqrt(mode_norm(k))) * r[k];
-        }
+            for (int m = 0; m < 4; ++m) {
+                const int k = 4 * j + m;
+                if (k >= 15) continue;
+                const T nzk = T(k == 0 ? B.nz_b : (k < 6 ? B.nz_s : B.nz_g));
+                const T amp = sr * nzk * T(1.0 / __builtin_sqrt(mode_norm(k))) * r[m];
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            T a = 0;
-#pragma unroll
-            for (int k = 0; k < 15; ++k) {
-                const int e = emode(k, i);
-                if (e != 0) a += T(e) * amp[k];
+                for (int i = 0; i < NQ; ++i) {
+                    const int e = emode(k, i);
+                    if (e != 0) br[i] += T(e) * amp;
+                }
             }
-            br[i] += a;
         }
     }
 
@@ -294,8 +302,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const unsigned n = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
     if (valid) {
         if constexpr (ST == ST_MOM32) {
-            const T piece[MP_N] = {base, T(3) * ax, T(3) * ay, T(3) * az, T(4.5) * Bxx, T(4.5) * Byy, T(4.5) * Bzz,
-                                   T(9) * Bxy, T(9) * Bxz, T(9) * Byz};
+            const T piece[MP_N] = {base, a3x, a3y, a3z, bxx, byy, bzz, bxy, bxz, byz};
 #pragma unroll
             for (int k = 0; k < MP_N; ++k)
                 bstore<S, 2>(piece[k], plane_rsrc(db + (long long)k * G.sp, pbytes), n * unsigned(sizeof(S)));
