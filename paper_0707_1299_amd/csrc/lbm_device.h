@@ -245,14 +245,20 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
     constexpr int AUX = NTL ? 2 : 0;
+    // FP16: the stored value, converted exactly; the weight is applied after the load
+    auto value = [](int i, S v) -> T {
+        (void)i;
+        return T(v);
+    };
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
         const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
         const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
         const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
-        const unsigned off = ((unsigned(sz) * unsigned(ny) + unsigned(sy)) * unsigned(nx) + unsigned(sx)) * unsigned(sizeof(S));
+        const unsigned row = (unsigned(sz) * unsigned(ny) + unsigned(sy)) * unsigned(nx);
         if constexpr (ST == ST_MOM32) {
+            const unsigned off = (row + unsigned(sx)) * unsigned(sizeof(S));
             auto piece = [&](int k) { return bload<S, AUX>(plane_rsrc(sb + (long long)k * sp, pbytes), off); };
             T br = piece(MP_R0);
             if (cx != 0) br += (cx > 0 ? piece(MP_AX) : -piece(MP_AX)) + piece(MP_BXX);
@@ -263,12 +269,10 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
             if (cy * cz != 0) br += cy * cz > 0 ? piece(MP_BYZ) : -piece(MP_BYZ);
             f[i] = T(wgt(i)) * br;
         } else {
-            const S v = bload<S, AUX>(plane_rsrc(sb + (long long)i * sp, pbytes), off);
-            if constexpr (ST == ST_FP16)
-                f[i] = float(v) * float(wgt(i));
-            else
-                f[i] = v;
+            const unsigned off = (row + unsigned(sx)) * unsigned(sizeof(S));
+            f[i] = value(i, bload<S, AUX>(plane_rsrc(sb + (long long)i * sp, pbytes), off));
         }
+        if constexpr (ST == ST_FP16) f[i] = f[i] * float(wgt(i));
     }
 }
 
