@@ -263,6 +263,31 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
     return r, (shape, storage, tau, kind, n, pos, frc, fkind, model)
 
 
+def stream_copy_gbs(nbytes, reps=20):
+    """Measured HBM copy rate (read + write bytes / time, GB/s) of the library's streaming-copy probe
+    over nbytes, timed with HIP events on the stream it runs on: the practical ceiling a streaming
+    kernel is set against beside the vendor peak."""
+    import torch
+    from paper_0707_1299_amd import lbm
+    nbytes = (nbytes + 15) // 16 * 16
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        lbm.lb_copy_probe(src, dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        lbm.lb_copy_probe(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    assert bool(torch.equal(src, dst))
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def describe(name, r):
     shape, storage, tau, kind, n = WORKLOADS[name]
     if kind == "singularities":
@@ -308,6 +333,8 @@ def main():
     from paper_0707_1299_amd import lbm  # noqa: F401  (fails loudly if the library is missing)
 
     r, inp = run_workload(a.workload, a.steps, a.warmup, a.timing_steps)
+    same_bytes = BYTES_PER_NODE[inp[1]] * r["nodes"] // 2          # one population copy of the workload
+    copy_gbs, copy_same_gbs = stream_copy_gbs(1 << 30), stream_copy_gbs(same_bytes)
     shape, storage, tau, kind, n, pos, frc, fkind, model = inp
     traffic = traffic_from_profile(a.workload, storage, r["nodes"])
     tile, variant = tuned(shape, storage)
@@ -331,7 +358,10 @@ def main():
                      "frac": round(r["frac"], 4), "traffic": traffic,
                      "kernel": "k_lattice step (fused spread/pull/collide/store/interpolate)",
                      "bytes_per_node": BYTES_PER_NODE[storage], "kernel_ms": round(r["kernel_ms"], 5),
-                     "launches_timed": r["launches_timed"]},
+                     "launches_timed": r["launches_timed"],
+                     "copy_1GiB_GBs": round(copy_gbs, 1), "frac_of_copy": round(r["achieved_GBs"] / copy_gbs, 4),
+                     "copy_same_bytes_GBs": round(copy_same_gbs, 1),
+                     "frac_of_copy_same_bytes": round(r["achieved_GBs"] / copy_same_gbs, 4)},
     }
     if "colloid_updates_per_s" in r:
         out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)

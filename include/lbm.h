@@ -294,6 +294,18 @@ int lb_kernel_timing(lb_ctx* ctx, int enable);
 int lb_kernel_time(lb_ctx* ctx, double* total_ms, int64_t* launches);
 
 /*
+ * Streaming-copy probe (a measurement aid, not an operation of the method):
+ * copies `bytes` from d_src to d_dst (device pointers, both 16-byte aligned,
+ * non-overlapping, bytes a positive multiple of 16), 16 bytes per thread with
+ * non-temporal loads and stores, enqueued on hip_stream (NULL = default
+ * stream).  Timed by the caller, it gives the practical HBM copy rate against
+ * which the fused step kernel's bandwidth is set beside the vendor peak.
+ * Errors: LB_ERR_ARG (alignment, size, overlap), LB_ERR_SIZE (grid too large),
+ * LB_ERR_HIP (launch failure).
+ */
+int lb_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
+
+/*
  * Multipoles of Sec. III as point forces (HOST arrays, host computation).
  * type[i]: 0 Stokeslet (s p at R), 1 stresslet (+s p at R + d/2 p and
  * -s p at R - d/2 p), 2 rotlet (with e2 = n x e1: +s e2 at R + d/2 e1,

@@ -123,6 +123,7 @@ def _load():
         "lb_steps_taken": (i64, [vp]),
         "lb_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "lb_kernel_time": (ctypes.c_int, [vp, P(dbl), P(i64)]),
+        "lb_copy_probe": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         "lb_expand_multipoles": (ctypes.c_int, [i64, vp, vp, vp, vp, vp, dbl, P(i64), vp, vp]),
         "lbml_work_floats": (i64, [i64]),
         "lbml_round_bf16": (ctypes.c_int, [vp, vp, vp]),
@@ -391,5 +392,16 @@ def lbml_loss_grad(w16, x, target, grad, loss, work):
 def lbml_adam_step(master, m, v, grad, w16, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     r = _L.lbml_adam_step(_ptr(master), _ptr(m), _ptr(v), _ptr(grad), _ptr(w16), int(t), lr, beta1, beta2, eps,
                           _stream_handle())
+    if r != LB_OK:
+        raise LBError(r)
+
+
+def lb_copy_probe(src, dst, nbytes=None):
+    """Streaming copy of nbytes (default: all of src) from src to dst, device tensors, on torch's current
+    stream; a measurement aid for the HBM copy rate."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    if nbytes > dst.numel() * dst.element_size() or nbytes > src.numel() * src.element_size():
+        raise LBError(LB_ERR_ARG, "copy larger than a buffer")
+    r = _L.lb_copy_probe(_ptr(src), _ptr(dst), nbytes, _stream_handle())
     if r != LB_OK:
         raise LBError(r)

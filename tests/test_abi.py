@@ -91,3 +91,33 @@ def test_expand_multipoles_matches_oracle():
 def test_expand_multipoles_rejects_unknown_type():
     with pytest.raises(lbm.LBError):
         lbm.lb_expand_multipoles([5], np.zeros((1, 3)), np.ones((1, 3)), np.ones((1, 3)), [1.0], 2.0)
+
+
+def test_binding_fails_loudly_without_the_library():
+    """No CPU fallback: importing the binding with the library absent raises ImportError."""
+    import subprocess
+    import sys
+    code = (
+        "import os, sys\n"
+        "real = os.path.exists\n"
+        "os.path.exists = lambda p: False if str(p).endswith('liblbm.so') else real(p)\n"
+        "try:\n"
+        "    import paper_0707_1299_amd.lbm\n"
+        "except ImportError as e:\n"
+        "    print('IMPORT_ERROR', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "IMPORT_ERROR" in r.stdout
+
+
+def test_copy_probe_rejects_bad_arguments_before_any_launch():
+    """Argument checks of the streaming-copy probe run on the host: nothing is launched."""
+    lib = lbm._L
+    bad = [(0, 1 << 20, 64), (1 << 20, 0, 64), (1 << 20, 1 << 21, 0), (1 << 20, 1 << 21, 24),
+           (1 << 20 | 8, 1 << 21, 64), (1 << 20, (1 << 21) | 4, 64), (1 << 20, (1 << 20) + 32, 64),
+           ((1 << 20) + 32, 1 << 20, 64)]
+    for s, d, n in bad:
+        assert lib.lb_copy_probe(ctypes.c_void_p(s), ctypes.c_void_p(d), n, None) == lbm.LB_ERR_ARG, (s, d, n)
