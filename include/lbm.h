@@ -95,11 +95,13 @@ typedef struct lb_params {
     int32_t tile_z;
     int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default */
     int32_t variant;        /* step-kernel variant bits (same results, different memory access):
-                               1 = 64-bit per-lane addresses instead of scalar plane bases
-                                   plus 32-bit lane offsets,
+                               1 = 64-bit per-lane addresses instead of scalar
+                                   descriptors plus 32-bit lane offsets,
                                2 = cached instead of non-temporal population loads,
                                4 * k (k = 0..3) = each block of the step kernel works
-                                   through 2^k consecutive tiles.
+                                   through 2^k consecutive tiles,
+                               16 = blocks take tiles in launch order instead of
+                                   contiguous runs of tiles per XCD.
                                With LB_STORAGE_MOM32 bits 0 and 1 have no effect: each
                                node gathers the pieces of its 18 neighbours with cached
                                buffer loads. */

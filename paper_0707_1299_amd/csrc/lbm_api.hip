@@ -68,9 +68,10 @@ void choose_tile(const lb_params* p, int& tx, int& ty, int& tz)
         tz = p->tile_z;
         return;
     }
+    const double box_bytes = double(p->nx) * p->ny * p->nz * planes_of(p->storage) * storage_bytes(p->storage);
     if (p->storage == LB_STORAGE_MOM32 && p->nx >= 128) {
         tx = 128; ty = 1; tz = 2;   // long x rows: the gathered pieces are re-read from L1
-    } else if (p->nx >= 64) {
+    } else if (p->nx >= 64 || box_bytes >= 4.0e9) {
         tx = 64; ty = 2; tz = 2;
     } else if (p->nx >= 32) {
         tx = 32; ty = 4; tz = 2;
@@ -87,7 +88,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_MOM32) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
-    if (p->variant < 0 || p->variant > 15) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if (p->variant < 0 || p->variant > 31) { why = "unknown kernel variant"; return LB_ERR_ARG; }
     if (p->collision < LB_COLLISION_PROJECTED || p->collision > LB_COLLISION_MRT) {
         why = "unknown collision operator";
         return LB_ERR_ARG;
@@ -117,8 +118,23 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.nty = (p->ny + ty - 1) / ty;
     G.ntz = (p->nz + tz - 1) / tz;
     G.N = (long long)p->nx * p->ny * p->nz;
-    G.sp = (G.N + 255) / 256 * 256 + 64;
-    G.sbox = (long long)planes_of(p->storage) * G.sp;
+    if (row_layout(p->storage)) {
+        G.kp = p->nx;
+        G.rb = (long long)planes_of(p->storage) * p->nx;
+        G.sbox = ((long long)p->ny * p->nz * G.rb + 255) / 256 * 256 + 64;
+    } else {
+        G.rb = p->nx;
+        G.kp = (G.N + 255) / 256 * 256 + 64;
+        G.sbox = (long long)planes_of(p->storage) * G.kp;
+        if ((unsigned long long)G.kp * storage_bytes(p->storage) >= (1ULL << 32)) {
+            why = "box too large: a population plane must stay under 4 GiB";
+            return LB_ERR_SIZE;
+        }
+    }
+    if (tx < 64 && (unsigned long long)G.sbox * storage_bytes(p->storage) >= (1ULL << 32)) {
+        why = "tiles narrower than 64 nodes in x need a box of under 4 GiB";
+        return LB_ERR_ARG;
+    }
     G.tiles_per_box = (long long)G.ntx * G.nty * G.ntz;
     G.ntiles = G.tiles_per_box * p->nboxes;
     G.rho0 = p->rho0 > 0.0 ? p->rho0 : 1.0;
@@ -132,6 +148,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (G.maxp > (1 << PK_BITS)) { why = "tile too small for the stencil"; return LB_ERR_ARG; }
     G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
     G.tpb = 1 << ((p->variant >> 2) & 3);
+    G.order = (p->variant >> 4) & 1;
     G.coll = p->kT > 0.0 ? 2 : (p->collision != LB_COLLISION_PROJECTED ? 1 : 0);
     G.seed_lo = uint32_t(p->seed);
     G.seed_hi = uint32_t(p->seed >> 32);

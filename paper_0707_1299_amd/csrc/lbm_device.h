@@ -93,11 +93,13 @@ struct Geom {
     int maxp;             // max tiles touched by one point's stencil
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
+    int order;            // 0: blocks renumbered into contiguous runs per XCD; 1: launch order
     int coll;             // 1: general collision (bulk rate, ghost moments kept); 2: with thermal noise
     unsigned seed_lo, seed_hi;   // key of the noise generator
     long long N;          // nodes per box
-    long long sp;         // elements between population planes
-    long long sbox;       // elements between boxes (NQ * sp)
+    long long rb;         // elements between consecutive rows of one plane (see pop_index)
+    long long kp;         // elements between consecutive planes of one row
+    long long sbox;       // elements between boxes
     long long tiles_per_box;
     long long ntiles;
     double rho0;
@@ -194,11 +196,11 @@ __device__ __forceinline__ void peskin4(double f, double (&w)[4])
     w[3] = (1.0 + 2.0 * f - q) * 0.125;
 }
 
-// Raw buffer access: a wave-uniform descriptor per population plane (scalar
-// registers) and a 32-bit byte offset per lane.  The descriptor's record count
-// is the plane size, so an offset past the plane reads 0 / drops the store
-// instead of touching other memory.  Dword 3 is the gfx9-family value; aux
-// bit 1 marks the access non-temporal.
+// Raw buffer access: a wave-uniform descriptor (scalar registers) over a row
+// block, a plane or a whole box, and a 32-bit byte offset per lane.  The descriptor's
+// record count is the size of that range, so an offset past it reads 0 / drops
+// the store instead of touching other memory.  Dword 3 is the gfx9-family
+// value; aux bit 1 marks the access non-temporal.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
 __device__ __forceinline__ rsrc_t plane_rsrc(const void* base, unsigned bytes)
@@ -207,28 +209,100 @@ __device__ __forceinline__ rsrc_t plane_rsrc(const void* base, unsigned bytes)
 }
 
 template <class S, int AUX>
-__device__ __forceinline__ S bload(rsrc_t r, unsigned off)
+__device__ __forceinline__ S bload(rsrc_t r, unsigned off, unsigned soff = 0)
 {
     if constexpr (sizeof(S) == 8)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, AUX));
     else if constexpr (sizeof(S) == 4)
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, AUX));
     else
-        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+        return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, AUX));
 }
 
 template <class S, int AUX>
-__device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned off)
+__device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned off, unsigned soff = 0)
 {
     if constexpr (sizeof(S) == 8)
     {
         typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, AUX);
     }
     else if constexpr (sizeof(S) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, AUX);
     else
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, AUX);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, soff, AUX);
+}
+
+// Layout of the population copies.  Element (plane k, x) of row r = z ny + y
+// of a box is at r rb + k kp + x, in one of two arrangements:
+//  * row-interleaved (FP64, FP32, moment storage): each row keeps its planes
+//    (the 19 populations, or the 10 moment pieces) as consecutive segments of
+//    nx values, kp = nx, rb = planes nx.  A pull then reads, for each of the
+//    few upstream rows, one contiguous block of memory instead of 19 planes
+//    far apart, which keeps HBM streaming close to the rate of a plain copy;
+//  * separate planes (scaled FP16, where this measured faster): rb = nx and
+//    kp = the plane size padded to a multiple of 256 elements plus 64.
+__host__ __device__ constexpr bool row_layout(int st) { return st != ST_FP16; }
+
+__host__ __device__ __forceinline__ long long pop_index(long long rb, long long kp, int k, long long row, int x)
+{
+    return row * rb + (long long)k * kp + x;
+}
+
+// Addressing of the population copies by the lattice kernels:
+//   A_ROW:   all lanes of a wave on one row (tiles at least 64 nodes wide in x).
+//            Row-interleaved: one descriptor per row block in scalar registers,
+//            lane offset x, plane offset k kp as the scalar offset operand.
+//            Separate planes: one descriptor per plane, lane offset r nx + x;
+//   A_BOX32: one descriptor at the box start, lane offset r rb + x, scalar
+//            offset k kp (boxes under 4 GiB);
+//   A_G64:   global accesses with 64-bit per-lane addresses (any box size).
+// The descriptors' record counts bound every access to its row block, plane or box.
+enum Addr { A_ROW = 0, A_BOX32 = 1, A_G64 = 2 };
+
+template <class S, bool ROWS, bool NTL, int ADDR>
+__device__ __forceinline__ S load_pop(const S* __restrict__ sb, long long rb, long long kp, unsigned box_bytes, int k,
+                                      unsigned row, int x)
+{
+    constexpr int AUX = NTL ? 2 : 0;
+    constexpr unsigned E = sizeof(S);
+    if constexpr (ADDR == A_ROW && ROWS) {
+        const unsigned srow = __builtin_amdgcn_readfirstlane(row);
+        return bload<S, AUX>(plane_rsrc(sb + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * E), unsigned(x) * E,
+                             unsigned(k) * unsigned(kp) * E);
+    } else if constexpr (ADDR == A_ROW) {
+        return bload<S, AUX>(plane_rsrc(sb + (long long)k * kp, unsigned(kp) * E),
+                             unsigned(pop_index(rb, kp, 0, row, x)) * E);
+    } else if constexpr (ADDR == A_BOX32) {
+        return bload<S, AUX>(plane_rsrc(sb, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * E,
+                             unsigned(k) * unsigned(kp) * E);
+    } else {
+        const S* p = sb + pop_index(rb, kp, k, row, x);
+        if constexpr (NTL)
+            return __builtin_nontemporal_load(p);
+        else
+            return *p;
+    }
+}
+
+// Non-temporal store of one value (same addressing modes as load_pop).
+template <class S, bool ROWS, int ADDR>
+__device__ __forceinline__ void store_pop(S v, S* __restrict__ db, long long rb, long long kp, unsigned box_bytes, int k,
+                                          unsigned row, int x)
+{
+    constexpr unsigned E = sizeof(S);
+    if constexpr (ADDR == A_ROW && ROWS) {
+        const unsigned srow = __builtin_amdgcn_readfirstlane(row);
+        bstore<S, 2>(v, plane_rsrc(db + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * E), unsigned(x) * E,
+                     unsigned(k) * unsigned(kp) * E);
+    } else if constexpr (ADDR == A_ROW) {
+        bstore<S, 2>(v, plane_rsrc(db + (long long)k * kp, unsigned(kp) * E), unsigned(pop_index(rb, kp, 0, row, x)) * E);
+    } else if constexpr (ADDR == A_BOX32) {
+        bstore<S, 2>(v, plane_rsrc(db, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * E,
+                     unsigned(k) * unsigned(kp) * E);
+    } else {
+        __builtin_nontemporal_store(v, db + pop_index(rb, kp, k, row, x));
+    }
 }
 
 // The 19 pre-collision populations of node (x, y, z) as deviations (for FP16
@@ -237,29 +311,24 @@ __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned off)
 // periodic neighbours of x, y, z.  The populations layout reads one value per
 // direction; the moment layout rebuilds each population from the upstream
 // node's stored bracket pieces.
-template <int ST, bool NTL>
-__device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restrict__ sb, long long sp, unsigned pbytes,
-                                          int ny, int nx, int x, int y, int z, int xm, int xp, int ym, int yp,
-                                          int zm, int zp, typename StoreT<ST>::T (&f)[NQ])
+template <int ST, bool NTL, int ADDR>
+__device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restrict__ sb, long long rb, long long kp,
+                                          unsigned box_bytes, int ny, int x, int y, int z, int xm, int xp, int ym,
+                                          int yp, int zm, int zp, typename StoreT<ST>::T (&f)[NQ])
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
-    constexpr int AUX = NTL ? 2 : 0;
-    // FP16: the stored value, converted exactly; the weight is applied after the load
-    auto value = [](int i, S v) -> T {
-        (void)i;
-        return T(v);
-    };
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
         const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
         const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
         const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
-        const unsigned row = (unsigned(sz) * unsigned(ny) + unsigned(sy)) * unsigned(nx);
+        const unsigned row = unsigned(sz) * unsigned(ny) + unsigned(sy);
+        auto piece = [&](int k) -> T {
+            return T(load_pop<S, row_layout(ST), NTL, ADDR>(sb, rb, kp, box_bytes, k, row, sx));
+        };
         if constexpr (ST == ST_MOM32) {
-            const unsigned off = (row + unsigned(sx)) * unsigned(sizeof(S));
-            auto piece = [&](int k) { return bload<S, AUX>(plane_rsrc(sb + (long long)k * sp, pbytes), off); };
             T br = piece(MP_R0);
             if (cx != 0) br += (cx > 0 ? piece(MP_AX) : -piece(MP_AX)) + piece(MP_BXX);
             if (cy != 0) br += (cy > 0 ? piece(MP_AY) : -piece(MP_AY)) + piece(MP_BYY);
@@ -269,10 +338,10 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
             if (cy * cz != 0) br += cy * cz > 0 ? piece(MP_BYZ) : -piece(MP_BYZ);
             f[i] = T(wgt(i)) * br;
         } else {
-            const unsigned off = (row + unsigned(sx)) * unsigned(sizeof(S));
-            f[i] = value(i, bload<S, AUX>(plane_rsrc(sb + (long long)i * sp, pbytes), off));
+            // FP16: the stored value, converted exactly, then weighted
+            f[i] = piece(i);
+            if constexpr (ST == ST_FP16) f[i] = f[i] * float(wgt(i));
         }
-        if constexpr (ST == ST_FP16) f[i] = f[i] * float(wgt(i));
     }
 }
 

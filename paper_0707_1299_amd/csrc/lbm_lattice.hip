@@ -33,6 +33,7 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
     const int box = int(gid / G.N);
     const long long n = gid % G.N;
     const int x = int(n % G.nx), y = int((n / G.nx) % G.ny), z = int(n / ((long long)G.nx * G.ny));
+    const long long row = n / G.nx;
     const double s = ST == ST_FP16 ? ldexp(1.0, boxes[box].e_data) : 1.0;
     S* db = dst + (long long)box * G.sbox;
     if constexpr (ST == ST_MOM32) {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
         const double piece[MP_N] = {(r - G.rho0) - 1.5 * r * uu, 3 * r * v[0], 3 * r * v[1], 3 * r * v[2],
                                     4.5 * r * v[0] * v[0], 4.5 * r * v[1] * v[1], 4.5 * r * v[2] * v[2],
                                     9 * r * v[0] * v[1], 9 * r * v[0] * v[2], 9 * r * v[1] * v[2]};
-        for (int k = 0; k < MP_N; ++k) db[k * G.sp + n] = S(piece[k]);
+        for (int k = 0; k < MP_N; ++k) db[pop_index(G.rb, G.kp, k, row, x)] = S(piece[k]);
         return;
     }
 #pragma unroll
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(BLOCK) void k_equilibrium(const Geom G, typename St
         const double cu = cvel(i, 0) * vx + cvel(i, 1) * vy + cvel(i, 2) * vz;
         const double uu = vx * vx + vy * vy + vz * vz;
         const double bracket = (r - G.rho0) + 3.0 * r * cu + 4.5 * r * (cu * cu - uu / 3.0);
-        db[i * G.sp + n] = ST == ST_FP16 ? S(bracket * s) : S(wgt(i) * bracket);
+        db[pop_index(G.rb, G.kp, i, row, x)] = ST == ST_FP16 ? S(bracket * s) : S(wgt(i) * bracket);
     }
 }
 

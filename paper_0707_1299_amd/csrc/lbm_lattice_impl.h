@@ -34,18 +34,8 @@ namespace lbm {
 enum Mode { M_STEP = 0, M_MOMENTS = 1, M_DIAG = 2 };
 
 
-template <bool NT, class S> __device__ __forceinline__ S ld(const S* p)
-{
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-template <class S> __device__ __forceinline__ void st(S* p, S v) { __builtin_nontemporal_store(v, p); }
-
 // VAR bit 0: global loads/stores with 64-bit per-lane addresses instead of
-// raw buffer accesses (scalar plane descriptor + 32-bit lane offset).
+// raw buffer accesses (scalar descriptor + 32-bit lane offset).
 // VAR bit 1: cached instead of non-temporal population loads.
 // COLL: 1 = general collision of Eq. mrtlbe (bulk mode at its own rate, ghost
 // moments multiplied by kappa_g instead of projected out); 2 = the same plus
@@ -83,29 +73,18 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const S* sb = src + (long long)box * G.sbox;
 
     // ---- pull: population i at x comes from x - c_i
-    // Each population plane is addressed as a wave-uniform buffer descriptor
-    // plus a 32-bit per-lane byte offset (a plane holds < 4 GiB).
+    // Addressing (see load_pop): a tile at least one wave wide in x keeps each wave on
+    // one row; narrower tiles address from the box start (boxes under 4 GiB, checked at
+    // set-up); variant bit 0 uses 64-bit global addresses.  The planes of FP16 storage
+    // stay separate (row_layout), the others are interleaved per row.
     constexpr bool WIDE = (VAR & 1);
+    constexpr int ADDR = WIDE ? A_G64 : (TX >= 64 ? A_ROW : A_BOX32);
     // moment pieces are re-read by up to 18 neighbours: always cached loads
     constexpr bool NTL = !(VAR & 2) && ST != ST_MOM32;
-    const unsigned pbytes = unsigned(G.sp * (long long)sizeof(S));
+    const unsigned box_bytes = unsigned(G.sbox * (long long)sizeof(S));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     T f[NQ];
-    if constexpr (WIDE && ST != ST_MOM32) {
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const int sx = cvel(i, 0) > 0 ? xm : (cvel(i, 0) < 0 ? xp : x);
-            const int sy = cvel(i, 1) > 0 ? ym : (cvel(i, 1) < 0 ? yp : y);
-            const int sz = cvel(i, 2) > 0 ? zm : (cvel(i, 2) < 0 ? zp : z);
-            const S v = ld<NTL>(sb + i * G.sp + ((long long)sz * G.ny + sy) * G.nx + sx);
-            if constexpr (ST == ST_FP16)
-                f[i] = float(v) * float(wgt(i));
-            else
-                f[i] = v;
-        }
-    } else {
-        pull_node<ST, NTL>(sb, G.sp, pbytes, G.ny, G.nx, x, y, z, xm, xp, ym, yp, zm, zp, f);
-    }
+    pull_node<ST, NTL, ADDR>(sb, G.rb, G.kp, box_bytes, G.ny, x, y, z, xm, xp, ym, yp, zm, zp, f);
 
     // ---- moments (10 values), over opposite pairs (i, i+1): the pair sum feeds the even
     // moments (mass, second moments), the difference the odd ones (momentum)
@@ -299,13 +278,12 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 
     // ---- store the post-collision state of this node
     S* db = dst + (long long)box * G.sbox;
-    const unsigned n = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
+    const unsigned row = unsigned(z) * unsigned(G.ny) + unsigned(y);
     if (valid) {
         if constexpr (ST == ST_MOM32) {
             const T piece[MP_N] = {base, a3x, a3y, a3z, bxx, byy, bzz, bxy, bxz, byz};
 #pragma unroll
-            for (int k = 0; k < MP_N; ++k)
-                bstore<S, 2>(piece[k], plane_rsrc(db + (long long)k * G.sp, pbytes), n * unsigned(sizeof(S)));
+            for (int k = 0; k < MP_N; ++k) store_pop<S, row_layout(ST), ADDR>(piece[k], db, G.rb, G.kp, box_bytes, k, row, x);
         } else {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
@@ -314,10 +292,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                     v = S(br[i] * B.s_out);
                 else
                     v = S(T(wgt(i)) * br[i]);
-                if constexpr (WIDE)
-                    st(db + i * G.sp + (long long)n, v);
-                else
-                    bstore<S, 2>(v, plane_rsrc(db + (long long)i * G.sp, pbytes), n * unsigned(sizeof(S)));
+                store_pop<S, row_layout(ST), ADDR>(v, db, G.rb, G.kp, box_bytes, i, row, x);
             }
         }
     }
@@ -378,8 +353,9 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     }
 }
 
-// One block per run of G.tpb consecutive tiles (blocks renumbered so that the
-// runs of one XCD are contiguous); each tile is finished before the next.
+// One block per run of G.tpb consecutive tiles (unless G.order is set, blocks are
+// renumbered so that the runs of one XCD are contiguous); each tile is finished
+// before the next.
 // With COLL == 2 the block of tile 0 also advances the step counter for the next
 // step (*tout = *tin + 1; the two slots alternate with the population copies).
 template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
@@ -392,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
                                                    const unsigned long long* __restrict__ tin,
                                                    unsigned long long* __restrict__ tout)
 {
-    const int first = xcd_tile(blockIdx.x, gridDim.x) * G.tpb;
+    const int first = (G.order ? int(blockIdx.x) : xcd_tile(blockIdx.x, gridDim.x)) * G.tpb;
     const int last = min((long long)first + G.tpb, G.ntiles);
     for (int tile = first; tile < last; ++tile)
         lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1, tin);

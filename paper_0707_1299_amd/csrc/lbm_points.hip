@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_interp_points(const Geom G, long long n
     const auto* sb = src + (long long)box * G.sbox;
     const BoxDev& B = boxes[box];
     T f[NQ];
-    pull_node<ST, false>(sb, G.sp, unsigned(G.sp * (long long)sizeof(*sb)), G.ny, G.nx, x, y, z, xm, xp, ym, yp, zm, zp,
+    pull_node<ST, false, A_G64>(sb, G.rb, G.kp, 0u, G.ny, x, y, z, xm, xp, ym, yp, zm, zp,
                          f);
     T drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll

@@ -22,7 +22,7 @@ CACHE = os.path.join(HERE, "tune_cache.json")
 ARCH = "gfx950"
 TILES = [(64, 2, 2), (64, 4, 1), (64, 1, 4), (128, 2, 1), (128, 1, 2), (256, 1, 1), (32, 4, 2), (32, 2, 4),
          (16, 4, 4)]
-VARIANTS = [0, 2, 4, 6, 8, 10]
+VARIANTS = [0, 2, 4, 6, 8, 10, 16, 18, 20, 22]
 
 
 def key(shape, storage, nboxes):
@@ -39,11 +39,16 @@ def lookup(shape, storage, nboxes=1):
     return tuple(d["tile"]), int(d["variant"])
 
 
+PLANES = {"fp64": 19, "fp32": 19, "fp16": 19, "mom32": 10}
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "mom32": 4}
+
+
 def candidates(shape, storage="fp32"):
-    nx = shape[2]
+    nz, ny, nx = shape
+    big = nx * ny * nz * PLANES[storage] * ELEM_BYTES[storage] >= 4.0e9   # tiles under 64 wide need < 4 GiB boxes
     out = []
     for t in TILES:
-        if t[0] > 2 * nx:
+        if t[0] > 2 * nx or (big and t[0] < 64):
             continue
         for v in VARIANTS:
             out.append((t, v))
