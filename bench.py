@@ -73,7 +73,7 @@ DESCR = {
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lbm_lattice_impl.h", "lbm_device.h", "lbm_noise.h"):
+    for f in ("lbm_lattice_impl.h", "lbm_device.h", "lbm_noise.h", "lbm_api.hip"):
         h.update(open(os.path.join(ROOT, "paper_0707_1299_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -162,6 +162,10 @@ def traffic_from_profile(name, storage, N):
         return None
     d = json.load(open(path))
     if d.get("kernel_sha") != kernel_source_hash():
+        return None
+    shape = WORKLOADS[name][0]
+    tile, variant = tuned(shape, storage, WORKLOADS[name][4] if WORKLOADS[name][3] == "boxes" else 1)
+    if list(tile or []) != d.get("tile") or variant != d.get("variant"):
         return None
     return d.get("bytes_per_launch")
 
@@ -318,13 +322,16 @@ def main():
         import torch
         src = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        from paper_0707_1299_amd import lbm
         for _ in range(10):
             dst.copy_(src)
+        for _ in range(10):
+            lbm.lb_copy_probe(src, dst)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each": 1 << 29, "copies": 10}))
+        print(json.dumps({"copy_bytes_each": 1 << 29, "copies": 10, "kernels": ["torch copy_", "lb_copy_probe"]}))
         return
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU decomposition in this build "
+        print("bench.py runs on one GPU only: the library has no multi-GPU decomposition "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
 
