@@ -93,7 +93,8 @@ typedef struct lb_params {
     int32_t tile_x;         /* tile shape (nodes); 0 = default. tile_x*tile_y*tile_z = 256 */
     int32_t tile_y;
     int32_t tile_z;
-    int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default */
+    int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default (30, or from
+                               the thermal amplitude when kT > 0) */
     int32_t variant;        /* step-kernel variant bits (same results, different memory access):
                                1 = 64-bit per-lane addresses instead of scalar
                                    descriptors plus 32-bit lane offsets,
@@ -101,7 +102,11 @@ typedef struct lb_params {
                                4 * k (k = 0..3) = each block of the step kernel works
                                    through 2^k consecutive tiles,
                                16 = blocks take tiles in launch order instead of
-                                   contiguous runs of tiles per XCD.
+                                   contiguous runs of tiles per XCD,
+                               32 = FP16 storage: one node per lane in the step
+                                   kernel (by default, with nx even, each lane
+                                   takes two adjacent x nodes with 32-bit
+                                   accesses).
                                With LB_STORAGE_MOM32 bits 0 and 1 have no effect: each
                                node gathers the pieces of its 18 neighbours with cached
                                buffer loads. */

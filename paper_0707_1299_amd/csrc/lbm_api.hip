@@ -48,7 +48,7 @@ int max_axis_tiles(int n, int t)
 
 struct Layout {
     size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, tlist_tmp, pslot, partial, fpart, pmax, tmax, ticket, tctr,
-        err,
+        err, nf,
         diag, diagout;
     size_t total;
 };
@@ -71,7 +71,9 @@ void choose_tile(const lb_params* p, int& tx, int& ty, int& tz)
     const double box_bytes = double(p->nx) * p->ny * p->nz * planes_of(p->storage) * storage_bytes(p->storage);
     if (p->storage == LB_STORAGE_MOM32 && p->nx >= 128) {
         tx = 128; ty = 1; tz = 2;   // long x rows: the gathered pieces are re-read from L1
-    } else if (p->nx >= 64 || box_bytes >= 4.0e9) {
+    } else if (box_bytes >= 4.0e9) {
+        tx = 128; ty = 2; tz = 1;   // a whole wave on one row (also with two FP16 nodes per lane)
+    } else if (p->nx >= 64) {
         tx = 64; ty = 2; tz = 2;
     } else if (p->nx >= 32) {
         tx = 32; ty = 4; tz = 2;
@@ -88,7 +90,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_MOM32) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
-    if (p->variant < 0 || p->variant > 31) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if (p->variant < 0 || p->variant > 63) { why = "unknown kernel variant"; return LB_ERR_ARG; }
     if (p->collision < LB_COLLISION_PROJECTED || p->collision > LB_COLLISION_MRT) {
         why = "unknown collision operator";
         return LB_ERR_ARG;
@@ -118,22 +120,20 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.nty = (p->ny + ty - 1) / ty;
     G.ntz = (p->nz + tz - 1) / tz;
     G.N = (long long)p->nx * p->ny * p->nz;
-    if (row_layout(p->storage)) {
-        G.kp = p->nx;
-        G.rb = (long long)planes_of(p->storage) * p->nx;
-        G.sbox = ((long long)p->ny * p->nz * G.rb + 255) / 256 * 256 + 64;
-    } else {
-        G.rb = p->nx;
-        G.kp = (G.N + 255) / 256 * 256 + 64;
-        G.sbox = (long long)planes_of(p->storage) * G.kp;
-        if ((unsigned long long)G.kp * storage_bytes(p->storage) >= (1ULL << 32)) {
-            why = "box too large: a population plane must stay under 4 GiB";
-            return LB_ERR_SIZE;
+    G.kp = p->nx;
+    G.rb = (long long)planes_of(p->storage) * p->nx;
+    G.sbox = ((long long)p->ny * p->nz * G.rb + 255) / 256 * 256 + 64;
+    {
+        // lanes along x of one tile row: a wave on one row addresses each row block from
+        // its own descriptor; narrower rows of lanes address the box from one descriptor
+        // with 32-bit offsets
+        const bool pairs = p->storage == LB_STORAGE_FP16 && p->nx % 2 == 0 && !((p->variant >> 5) & 1);
+        const int lanes_x = pairs ? tx / 2 : tx;
+        if (lanes_x < 64 && (unsigned long long)G.sbox * storage_bytes(p->storage) >= (1ULL << 32)) {
+            why = "tiles with fewer than 64 lanes along x (64 nodes, or 128 with two FP16 nodes per lane) need a "
+                  "box of under 4 GiB";
+            return LB_ERR_ARG;
         }
-    }
-    if (tx < 64 && (unsigned long long)G.sbox * storage_bytes(p->storage) >= (1ULL << 32)) {
-        why = "tiles narrower than 64 nodes in x need a box of under 4 GiB";
-        return LB_ERR_ARG;
     }
     G.tiles_per_box = (long long)G.ntx * G.nty * G.ntz;
     G.ntiles = G.tiles_per_box * p->nboxes;
@@ -149,6 +149,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
     G.tpb = 1 << ((p->variant >> 2) & 3);
     G.order = (p->variant >> 4) & 1;
+    G.pairs = p->storage == LB_STORAGE_FP16 && p->nx % 2 == 0 && !((p->variant >> 5) & 1);
     G.coll = p->kT > 0.0 ? 2 : (p->collision != LB_COLLISION_PROJECTED ? 1 : 0);
     G.seed_lo = uint32_t(p->seed);
     G.seed_hi = uint32_t(p->seed >> 32);
@@ -175,6 +176,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.ticket = take(sizeof(unsigned) * p->nboxes);
     L.tctr = take(2 * sizeof(unsigned long long));
     L.err = take(sizeof(int) * 4);
+    L.nf = take(sizeof(int) * p->nboxes);
     L.diag = take(sizeof(double) * LBD_N * G.ntiles);
     L.diagout = take(sizeof(double) * LBD_N * p->nboxes);
     L.total = o;
@@ -243,6 +245,7 @@ struct lb_ctx {
     unsigned* ticket() const { return (unsigned*)(ws + P.L.ticket); }
     unsigned long long* tctr() const { return (unsigned long long*)(ws + P.L.tctr); }
     int* errw() const { return (int*)(ws + P.L.err); }
+    int* nf() const { return (int*)(ws + P.L.nf); }
     double* diag() const { return (double*)(ws + P.L.diag); }
     double* diagout() const { return (double*)(ws + P.L.diagout); }
 };
@@ -482,6 +485,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->p.tau_bulk = nullptr;   // read below, not kept
     c->P = P;
     c->ws = (char*)d_workspace;
+    c->P.G.nf = c->nf();
     c->stream = (hipStream_t)hip_stream;
     c->cap_stream = nullptr;
     c->cur = 0;
@@ -493,7 +497,14 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->timed_ms = 0.0;
     c->timed_launches = 0;
     c->steps = 0;
-    const int e0 = p->fp16_exponent != 0 ? p->fp16_exponent : 30;
+    int e0 = p->fp16_exponent != 0 ? p->fp16_exponent : 30;
+    if (p->fp16_exponent == 0 && p->kT > 0.0) {
+        // thermal populations from the first step on: per population the noise of the 15 modes
+        // has standard deviation at most sqrt(mu rho / w_i) <= 6 sqrt(mu rho) in units of w_i
+        // (completeness of the mode basis); keep 6 of those deviations under 2^14
+        const double amp = 36.0 * sqrt(3.0 * p->kT * P.G.rho0);
+        e0 = std::min(30, int(floor(log2(16384.0 / amp))));
+    }
     c->hboxes.resize(p->nboxes);
     for (int b = 0; b < p->nboxes; ++b) {
         BoxDev& B = c->hboxes[b];
@@ -531,6 +542,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     launch_fill_u32(c->tctr(), 4, 0u, s);
     launch_fill_u32(c->tmax(), G.ntiles, 0u, s);
     launch_fill_u32(c->errw(), 4, 0u, s);
+    launch_fill_u32(c->nf(), p->nboxes, 0u, s);
     r = hip_check(c, hipMemcpyAsync(c->boxes(), c->hboxes.data(), sizeof(BoxDev) * p->nboxes, hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
     if (!r) r = check_async(c);
@@ -724,9 +736,8 @@ static int read_flags(lb_ctx* c)
     int errw[4];
     int r = hip_check(c, hipMemcpyAsync(errw, c->errw(), sizeof(errw), hipMemcpyDeviceToHost, c->stream), "hipMemcpy");
     if (r) return r;
-    std::vector<BoxDev> hb(c->p.nboxes);
-    r = hip_check(c, hipMemcpyAsync(hb.data(), c->boxes(), sizeof(BoxDev) * c->p.nboxes, hipMemcpyDeviceToHost,
-                                    c->stream),
+    std::vector<int> nf(c->p.nboxes);
+    r = hip_check(c, hipMemcpyAsync(nf.data(), c->nf(), sizeof(int) * c->p.nboxes, hipMemcpyDeviceToHost, c->stream),
                   "hipMemcpy");
     if (r) return r;
     r = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -740,7 +751,7 @@ static int read_flags(lb_ctx* c)
         return fail(c, LB_ERR_NONFINITE, "non-finite point position or force");
     }
     for (int b = 0; b < c->p.nboxes; ++b)
-        if (hb[b].nonfinite) return fail(c, LB_ERR_NONFINITE, "non-finite value or FP16 overflow in box " + std::to_string(b));
+        if (nf[b]) return fail(c, LB_ERR_NONFINITE, "non-finite value or FP16 overflow in box " + std::to_string(b));
     return LB_OK;
 }
 

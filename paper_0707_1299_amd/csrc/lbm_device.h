@@ -81,8 +81,6 @@ struct alignas(16) BoxDev {
     float s_out;       // FP16: quantise multiplier 2^e of the data written this step
     int e_data;        // FP16: exponent of the data currently stored
     unsigned spare;
-    int nonfinite;     // sticky: non-finite value or FP16 overflow seen
-    int pad;
 };
 
 // Geometry of the lattice and its tiles (all boxes share it).
@@ -94,6 +92,8 @@ struct Geom {
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
     int order;            // 0: blocks renumbered into contiguous runs per XCD; 1: launch order
+    int pairs;            // FP16 step: two adjacent x nodes per lane (nx even)
+    int* nf;              // per box, sticky: non-finite value or FP16 overflow seen by a step
     int coll;             // 1: general collision (bulk rate, ghost moments kept); 2: with thermal noise
     unsigned seed_lo, seed_hi;   // key of the noise generator
     long long N;          // nodes per box
@@ -233,46 +233,46 @@ __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned off, unsigned sof
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, soff, AUX);
 }
 
-// Layout of the population copies.  Element (plane k, x) of row r = z ny + y
-// of a box is at r rb + k kp + x, in one of two arrangements:
-//  * row-interleaved (FP64, FP32, moment storage): each row keeps its planes
-//    (the 19 populations, or the 10 moment pieces) as consecutive segments of
-//    nx values, kp = nx, rb = planes nx.  A pull then reads, for each of the
-//    few upstream rows, one contiguous block of memory instead of 19 planes
-//    far apart, which keeps HBM streaming close to the rate of a plain copy;
-//  * separate planes (scaled FP16, where this measured faster): rb = nx and
-//    kp = the plane size padded to a multiple of 256 elements plus 64.
-__host__ __device__ constexpr bool row_layout(int st) { return st != ST_FP16; }
+// FP16 storage conversions: the stored value (exact in FP32) times w_i, and
+// f*_i / w_i times the scale 2^e rounded to FP16 (nearest even).  The compiler
+// may fuse the first product into the sums that follow it, and may do so
+// differently in different kernels: the one- and two-nodes-per-lane FP16 paths
+// agree to FP16 rounding, not bit for bit.
+__device__ __forceinline__ float fp16_in(_Float16 v, float w) { return float(v) * w; }
 
+__device__ __forceinline__ _Float16 fp16_out(float b, float s) { return _Float16(b * s); }
+
+// Layout of the population copies (row-interleaved): in a box, row r = z ny + y
+// keeps its planes (the 19 populations, or the 10 moment pieces) as consecutive
+// segments of nx values, so element (plane k, x) of row r is at r rb + k kp + x
+// with kp = nx and rb = planes nx.  A pull then reads, for each of the few
+// upstream rows, one contiguous block of memory instead of 19 planes far apart,
+// which keeps HBM streaming close to the rate of a plain copy.
 __host__ __device__ __forceinline__ long long pop_index(long long rb, long long kp, int k, long long row, int x)
 {
     return row * rb + (long long)k * kp + x;
 }
 
 // Addressing of the population copies by the lattice kernels:
-//   A_ROW:   all lanes of a wave on one row (tiles at least 64 nodes wide in x).
-//            Row-interleaved: one descriptor per row block in scalar registers,
-//            lane offset x, plane offset k kp as the scalar offset operand.
-//            Separate planes: one descriptor per plane, lane offset r nx + x;
+//   A_ROW:   all lanes of a wave on one row (tiles whose x extent covers a
+//            whole wave): one descriptor per row block in scalar registers,
+//            lane offset x, plane offset k kp as the scalar offset operand;
 //   A_BOX32: one descriptor at the box start, lane offset r rb + x, scalar
 //            offset k kp (boxes under 4 GiB);
 //   A_G64:   global accesses with 64-bit per-lane addresses (any box size).
-// The descriptors' record counts bound every access to its row block, plane or box.
+// The descriptors' record counts bound every access to its row block or box.
 enum Addr { A_ROW = 0, A_BOX32 = 1, A_G64 = 2 };
 
-template <class S, bool ROWS, bool NTL, int ADDR>
+template <class S, bool NTL, int ADDR>
 __device__ __forceinline__ S load_pop(const S* __restrict__ sb, long long rb, long long kp, unsigned box_bytes, int k,
                                       unsigned row, int x)
 {
     constexpr int AUX = NTL ? 2 : 0;
     constexpr unsigned E = sizeof(S);
-    if constexpr (ADDR == A_ROW && ROWS) {
+    if constexpr (ADDR == A_ROW) {
         const unsigned srow = __builtin_amdgcn_readfirstlane(row);
         return bload<S, AUX>(plane_rsrc(sb + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * E), unsigned(x) * E,
                              unsigned(k) * unsigned(kp) * E);
-    } else if constexpr (ADDR == A_ROW) {
-        return bload<S, AUX>(plane_rsrc(sb + (long long)k * kp, unsigned(kp) * E),
-                             unsigned(pop_index(rb, kp, 0, row, x)) * E);
     } else if constexpr (ADDR == A_BOX32) {
         return bload<S, AUX>(plane_rsrc(sb, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * E,
                              unsigned(k) * unsigned(kp) * E);
@@ -286,22 +286,118 @@ __device__ __forceinline__ S load_pop(const S* __restrict__ sb, long long rb, lo
 }
 
 // Non-temporal store of one value (same addressing modes as load_pop).
-template <class S, bool ROWS, int ADDR>
+template <class S, int ADDR>
 __device__ __forceinline__ void store_pop(S v, S* __restrict__ db, long long rb, long long kp, unsigned box_bytes, int k,
                                           unsigned row, int x)
 {
     constexpr unsigned E = sizeof(S);
-    if constexpr (ADDR == A_ROW && ROWS) {
+    if constexpr (ADDR == A_ROW) {
         const unsigned srow = __builtin_amdgcn_readfirstlane(row);
         bstore<S, 2>(v, plane_rsrc(db + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * E), unsigned(x) * E,
                      unsigned(k) * unsigned(kp) * E);
-    } else if constexpr (ADDR == A_ROW) {
-        bstore<S, 2>(v, plane_rsrc(db + (long long)k * kp, unsigned(kp) * E), unsigned(pop_index(rb, kp, 0, row, x)) * E);
     } else if constexpr (ADDR == A_BOX32) {
         bstore<S, 2>(v, plane_rsrc(db, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * E,
                      unsigned(k) * unsigned(kp) * E);
     } else {
         __builtin_nontemporal_store(v, db + pop_index(rb, kp, k, row, x));
+    }
+}
+
+// FP16 storage, two nodes per lane: the stored values of population k at nodes
+// x and x + 1 (x even, nx even) form one 32-bit word, node x in the low half.
+// Same addressing modes as load_pop with 32-bit accesses.
+template <bool NTL, int ADDR>
+__device__ __forceinline__ uint32_t load_pair(const _Float16* __restrict__ sb, long long rb, long long kp,
+                                              unsigned box_bytes, int k, unsigned row, int x)
+{
+    constexpr int AUX = NTL ? 2 : 0;
+    if constexpr (ADDR == A_ROW) {
+        const unsigned srow = __builtin_amdgcn_readfirstlane(row);
+        return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(sb + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * 2u),
+                                                    unsigned(x) * 2u, unsigned(k) * unsigned(kp) * 2u, AUX);
+    } else if constexpr (ADDR == A_BOX32) {
+        return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(sb, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * 2u,
+                                                    unsigned(k) * unsigned(kp) * 2u, AUX);
+    } else {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(sb + pop_index(rb, kp, k, row, x));
+        if constexpr (NTL)
+            return __builtin_nontemporal_load(p);
+        else
+            return *p;
+    }
+}
+
+template <int ADDR>
+__device__ __forceinline__ void store_pair(uint32_t v, _Float16* __restrict__ db, long long rb, long long kp,
+                                           unsigned box_bytes, int k, unsigned row, int x)
+{
+    if constexpr (ADDR == A_ROW) {
+        const unsigned srow = __builtin_amdgcn_readfirstlane(row);
+        __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(db + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * 2u),
+                                              unsigned(x) * 2u, unsigned(k) * unsigned(kp) * 2u, 2);
+    } else if constexpr (ADDR == A_BOX32) {
+        __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(db, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * 2u,
+                                              unsigned(k) * unsigned(kp) * 2u, 2);
+    } else {
+        __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(db + pop_index(rb, kp, k, row, x)));
+    }
+}
+
+// Pull for two nodes per lane (FP16): word i holds population i of nodes x and
+// x + 1, gathered from x - c_i and x + 1 - c_i.  A population moving in +x needs
+// the upper half of the pair to the left, one moving in -x the lower half of the
+// pair to the right.  With a whole wave on one tile row (LX >= 64) the neighbour
+// pairs come from the adjacent lanes by a DPP wave shift; the wave's first lane
+// takes the pair left of the wave, and its last lane (or the lane at the end of
+// the box row, in a ragged tile) the pair right of it, each from one load at a
+// wave-uniform address.  All loads are issued before the shifts, which wait for
+// them.  Narrower tiles load each lane's neighbour pair directly.  x is the
+// lane's even node, xl / xr the even nodes of the pairs to its left and right
+// (periodic wrap).
+template <int LX, bool NTL, int ADDR>
+__device__ __forceinline__ void pull_pairs(const _Float16* __restrict__ sb, long long rb, long long kp, unsigned box_bytes,
+                                           int ny, int nx, int x, int xl, int xr, int y, int z, int ym, int yp, int zm,
+                                           int zp, uint32_t (&w)[NQ])
+{
+    uint32_t own[NQ], edge[NQ];
+    const int lane = threadIdx.x & 63;
+    // wave-uniform edge pairs (used when LX >= 64): left of lane 0, right of lane 63
+    const int el = __builtin_amdgcn_readfirstlane(xl);
+    const int er = __builtin_amdgcn_readlane(xr, 63);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+        const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
+        const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
+        const unsigned row = unsigned(sz) * unsigned(ny) + unsigned(sy);
+        own[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, i, row, x);
+        if (cx != 0) {
+            const int xe = LX >= 64 ? (cx > 0 ? el : er) : (cx > 0 ? xl : xr);
+            edge[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, i, row, xe);
+        }
+    }
+    const bool first = lane == 0;
+    const bool last = lane == 63 || x + 2 == nx;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int cx = cvel(i, 0);
+        if (cx == 0) {
+            w[i] = own[i];
+        } else if (cx > 0) {
+            uint32_t prev = edge[i];
+            if constexpr (LX >= 64) {
+                prev = __builtin_amdgcn_update_dpp(0u, own[i], 0x138, 0xf, 0xf, false);   // wave_shr:1
+                if (first) prev = edge[i];
+            }
+            w[i] = __builtin_amdgcn_alignbit(own[i], prev, 16);    // (prev.hi, own.lo)
+        } else {
+            uint32_t next = edge[i];
+            if constexpr (LX >= 64) {
+                next = __builtin_amdgcn_update_dpp(0u, own[i], 0x130, 0xf, 0xf, false);   // wave_shl:1
+                if (last) next = edge[i];
+            }
+            w[i] = __builtin_amdgcn_alignbit(next, own[i], 16);    // (own.hi, next.lo)
+        }
     }
 }
 
@@ -326,7 +422,7 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
         const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
         const unsigned row = unsigned(sz) * unsigned(ny) + unsigned(sy);
         auto piece = [&](int k) -> T {
-            return T(load_pop<S, row_layout(ST), NTL, ADDR>(sb, rb, kp, box_bytes, k, row, sx));
+            return T(load_pop<S, NTL, ADDR>(sb, rb, kp, box_bytes, k, row, sx));
         };
         if constexpr (ST == ST_MOM32) {
             T br = piece(MP_R0);
@@ -337,10 +433,10 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
             if (cx * cz != 0) br += cx * cz > 0 ? piece(MP_BXZ) : -piece(MP_BXZ);
             if (cy * cz != 0) br += cy * cz > 0 ? piece(MP_BYZ) : -piece(MP_BYZ);
             f[i] = T(wgt(i)) * br;
+        } else if constexpr (ST == ST_FP16) {
+            f[i] = fp16_in(load_pop<S, NTL, ADDR>(sb, rb, kp, box_bytes, i, row, sx), float(wgt(i)));
         } else {
-            // FP16: the stored value, converted exactly, then weighted
             f[i] = piece(i);
-            if constexpr (ST == ST_FP16) f[i] = f[i] * float(wgt(i));
         }
     }
 }

@@ -40,10 +40,11 @@ enum Mode { M_STEP = 0, M_MOMENTS = 1, M_DIAG = 2 };
 // COLL: 1 = general collision of Eq. mrtlbe (bulk mode at its own rate, ghost
 // moments multiplied by kappa_g instead of projected out); 2 = the same plus
 // thermal noise on the fifteen non-conserved modes, drawn for step *tin.
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1>
 __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                                              const typename StoreT<ST>::S* __restrict__ src,
-                                             typename StoreT<ST>::S* __restrict__ dst, BoxDev* __restrict__ boxes,
+                                             typename StoreT<ST>::S* __restrict__ dst,
+                                             const BoxDev* __restrict__ boxes,
                                              const int* __restrict__ toff, const int* __restrict__ tlist,
                                              const PRec<typename StoreT<ST>::T>* __restrict__ rec,
                                              double* __restrict__ out0, double* __restrict__ out1,
@@ -51,7 +52,12 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
-    static_assert(TX * TY * TZ == BLOCK, "one node per thread");
+    static_assert(TX * TY * TZ == BLOCK, "tiles of BLOCK nodes");
+    // NPL = 2: each lane takes the two adjacent nodes x, x + 1 (FP16 storage, nx even),
+    // half as many threads per tile
+    static_assert(NPL == 1 || (NPL == 2 && ST == ST_FP16 && MODE == M_STEP), "two nodes per lane: FP16 step only");
+    constexpr int LX = TX / NPL;              // lanes along x in a tile row
+    constexpr int NW = BLOCK / NPL / 64;      // waves per block
 
     int t = tile;
     const int itx = t % G.ntx;
@@ -60,11 +66,15 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     t /= G.nty;
     const int itz = t % G.ntz;
     const int box = t / G.ntz;
-    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-    const int x0 = itx * TX + lx, y0 = ity * TY + ly, z0 = itz * TZ + lz;
+    // a tile at least one wave wide puts each wave on one row: y and z are then wave-uniform
+    // and live in scalar registers (so do the upstream row indices of the pull)
+    const int tid_w = LX >= 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x)) : int(threadIdx.x);
+    const int lx = threadIdx.x % LX, ly = (tid_w / LX) % TY, lz = tid_w / (LX * TY);
+    const int x0 = itx * TX + lx * NPL, y0 = ity * TY + ly, z0 = itz * TZ + lz;
     const bool valid = (x0 < G.nx) & (y0 < G.ny) & (z0 < G.nz);
     // threads past a ragged edge work on a clamped in-range node and contribute nothing
-    const int x = min(x0, G.nx - 1), y = min(y0, G.ny - 1), z = min(z0, G.nz - 1);
+    // (with two nodes per lane nx is even, so x stays even and x + 1 is in range)
+    const int x = min(x0, G.nx - NPL), y = min(y0, G.ny - 1), z = min(z0, G.nz - 1);
     const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x + 1 == G.nx ? 0 : x + 1;
     const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y + 1 == G.ny ? 0 : y + 1;
     const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z + 1 == G.nz ? 0 : z + 1;
@@ -78,13 +88,40 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     // set-up); variant bit 0 uses 64-bit global addresses.  The planes of FP16 storage
     // stay separate (row_layout), the others are interleaved per row.
     constexpr bool WIDE = (VAR & 1);
-    constexpr int ADDR = WIDE ? A_G64 : (TX >= 64 ? A_ROW : A_BOX32);
+    constexpr int ADDR = WIDE ? A_G64 : (LX >= 64 ? A_ROW : A_BOX32);
     // moment pieces are re-read by up to 18 neighbours: always cached loads
     constexpr bool NTL = !(VAR & 2) && ST != ST_MOM32;
     const unsigned box_bytes = unsigned(G.sbox * (long long)sizeof(S));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    [[maybe_unused]] uint32_t wpair[NPL == 2 ? NQ : 1];
     T f[NQ];
-    pull_node<ST, NTL, ADDR>(sb, G.rb, G.kp, box_bytes, G.ny, x, y, z, xm, xp, ym, yp, zm, zp, f);
+    if constexpr (NPL == 2) {
+        const int xl = x == 0 ? G.nx - 2 : x - 2, xr = x + 2 == G.nx ? 0 : x + 2;
+        pull_pairs<LX, NTL, ADDR>(reinterpret_cast<const _Float16*>(sb), G.rb, G.kp, box_bytes, G.ny, G.nx, x, xl, xr,
+                                  y, z, ym, yp, zm, zp, wpair);
+    } else {
+        pull_node<ST, NTL, ADDR>(sb, G.rb, G.kp, box_bytes, G.ny, x, y, z, xm, xp, ym, yp, zm, zp, f);
+    }
+
+    int k0 = 0, k1 = 0;         // the tile's entries in the point lists (read below)
+    S* db = dst + (long long)box * G.sbox;
+    const unsigned row = unsigned(z) * unsigned(G.ny) + unsigned(y);
+    [[maybe_unused]] uint32_t opair[NPL == 2 ? NQ : 1];
+    bool bad = false;
+    T mx = 0;                     // FP16: largest |f*_i / w_i| of the lane's nodes
+    T uxs[NPL], uys[NPL], uzs[NPL];
+
+#pragma unroll
+    for (int h = 0; h < NPL; ++h) {
+    const int xh = x + h;
+    if constexpr (NPL == 2) {
+        // FP16 value of node xh (low half: x, high half: x + 1), converted exactly, then weighted
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const uint32_t bits = h == 0 ? (wpair[i] & 0xffffu) : (wpair[i] >> 16);
+            f[i] = fp16_in(__builtin_bit_cast(_Float16, uint16_t(bits)), float(wgt(i)));
+        }
+    }
 
     // ---- moments (10 values), over opposite pairs (i, i+1): the pair sum feeds the even
     // moments (mass, second moments), the difference the odd ones (momentum)
@@ -109,14 +146,13 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 
     // ---- force density at this node: counter-force + the tile's points
     T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
-    int k0 = 0, k1 = 0;
-    if (toff) {
+    if (h == 0 && toff) {
         k0 = toff[tile];
         k1 = toff[tile + 1];
     }
     for (int k = k0; k < k1; ++k) {
         const PRec<T>& r = rec[pk_point(tlist[k])];
-        const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
+        const T w = stencil_w<T>(xh, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
                     stencil_w<T>(z, r.bz, G.nz, r.wz);
         gx += r.f[0] * w;
         gy += r.f[1] * w;
@@ -252,7 +288,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2);
         // added here in units of w_i
         const unsigned long long t = *tin;
-        const uint32_t node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(x);
+        const uint32_t node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(xh);
         const T sr = sqrt(rho);
         // each call gives four normals for modes 4j .. 4j+3, applied at once (few live registers)
 #pragma unroll
@@ -276,61 +312,90 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         }
     }
 
-    // ---- store the post-collision state of this node
-    S* db = dst + (long long)box * G.sbox;
-    const unsigned row = unsigned(z) * unsigned(G.ny) + unsigned(y);
-    if (valid) {
+    // ---- health of this node: non-finite moments or forces (checked before the stores so
+    // that nothing after them waits on the stores)
+    {
+        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
+        bad = bad || (valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300)));
+    }
+
+    // ---- store the post-collision state of this node (two nodes per lane: packed below)
+    if constexpr (NPL == 2) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const uint32_t bits = __builtin_bit_cast(uint16_t, fp16_out(br[i], B.s_out));
+            opair[i] = h == 0 ? bits : (opair[i] | (bits << 16));
+        }
+    } else if (valid) {
         if constexpr (ST == ST_MOM32) {
             const T piece[MP_N] = {base, a3x, a3y, a3z, bxx, byy, bzz, bxy, bxz, byz};
 #pragma unroll
-            for (int k = 0; k < MP_N; ++k) store_pop<S, row_layout(ST), ADDR>(piece[k], db, G.rb, G.kp, box_bytes, k, row, x);
+            for (int k = 0; k < MP_N; ++k) store_pop<S, ADDR>(piece[k], db, G.rb, G.kp, box_bytes, k, row, x);
         } else {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 S v;
                 if constexpr (ST == ST_FP16)
-                    v = S(br[i] * B.s_out);
+                    v = fp16_out(br[i], B.s_out);
                 else
                     v = S(T(wgt(i)) * br[i]);
-                store_pop<S, row_layout(ST), ADDR>(v, db, G.rb, G.kp, box_bytes, i, row, x);
+                store_pop<S, ADDR>(v, db, G.rb, G.kp, box_bytes, i, row, x);
             }
         }
     }
 
-    // ---- health: non-finite values; FP16 range and the max for rescaling
-    {
-        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
-        bool bad = valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
-        if constexpr (ST == ST_FP16) {
-            T m = 0;
+    // ---- FP16: the largest stored magnitude, for the range check and the rescaling
+    if constexpr (ST == ST_FP16) {
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) m = fmax(m, fabs(br[i]));
-            if (!valid) m = 0;
-            bad = bad || (m * B.s_out > T(65504));
-            m = wave_max(m);
-            __shared__ float wm[4];
-            if (lane == 0) wm[wave] = m;
-            __syncthreads();
-            // per-tile maximum; the per-box reduction happens before the next step
-            if (threadIdx.x == 0) ((float*)out1)[tile] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
-            __syncthreads();   // wm is rewritten by the block's next tile
-        }
-        if (__any(bad) && lane == 0) atomicOr(&boxes[box].nonfinite, 1);
+        for (int i = 0; i < NQ; ++i) mx = fmax(mx, fabs(br[i]));
     }
+    uxs[h] = ux;
+    uys[h] = uy;
+    uzs[h] = uz;
+    }   // nodes of the lane
+
+    if constexpr (NPL == 2) {
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) store_pair<ADDR>(opair[i], reinterpret_cast<_Float16*>(db), G.rb, G.kp, box_bytes, i, row, x);
+        }
+    }
+    if constexpr (ST == ST_FP16) {
+        T m = valid ? mx : T(0);
+        bad = bad || (m * B.s_out > T(65504));
+        m = wave_max(m);
+        __shared__ float wm[NW];
+        if (lane == 0) wm[wave] = m;
+        __syncthreads();
+        // per-tile maximum; the per-box reduction happens before the next step
+        if (threadIdx.x == 0) {
+            float t = wm[0];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) t = fmaxf(t, wm[q]);
+            ((float*)out1)[tile] = t;
+        }
+        __syncthreads();   // wm is rewritten by the block's next tile
+    }
+    if (__any(bad) && lane == 0) atomicOr(&G.nf[box], 1);
 
     // ---- interpolation partial sums: sum over this tile's nodes of u * deltaP(x - R)
-    // u of the tile's nodes goes to LDS; wave w then takes the tile's points w, w + 4, ...,
+    // u of the tile's nodes goes to LDS; wave w then takes the tile's points w, w + NW, ...,
     // lane l standing for stencil node (l & 3, (l >> 2) & 3, l >> 4) of the point, and one
     // wave reduction per component gives the point's partial.
     if (k1 > k0) {
         __shared__ T su[3][BLOCK];
-        su[0][threadIdx.x] = valid ? ux : T(0);
-        su[1][threadIdx.x] = valid ? uy : T(0);
-        su[2][threadIdx.x] = valid ? uz : T(0);
+#pragma unroll
+        for (int h = 0; h < NPL; ++h) {
+            // node index in the tile
+            const int li = NPL == 1 ? int(threadIdx.x) : lx * NPL + h + TX * (ly + TY * lz);
+            su[0][li] = valid ? uxs[h] : T(0);
+            su[1][li] = valid ? uys[h] : T(0);
+            su[2][li] = valid ? uzs[h] : T(0);
+        }
         __syncthreads();
         const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
         const int x0 = itx * TX, y0 = ity * TY, z0 = itz * TZ;
-        for (int kk = k0 + wave; kk < k1; kk += BLOCK / 64) {
+        for (int kk = k0 + wave; kk < k1; kk += NW) {
             const PRec<T>& r = rec[pk_point(tlist[kk])];
             int gx = r.bx + dx, gy = r.by + dy, gz = r.bz + dz;
             if (gx >= G.nx) gx -= G.nx;
@@ -355,13 +420,13 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 
 // One block per run of G.tpb consecutive tiles (unless G.order is set, blocks are
 // renumbered so that the runs of one XCD are contiguous); each tile is finished
-// before the next.
+// before the next.  BLOCK / NPL threads per block.
 // With COLL == 2 the block of tile 0 also advances the step counter for the next
 // step (*tout = *tin + 1; the two slots alternate with the population copies).
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0>
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1>
 __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
-                                                   BoxDev* __restrict__ boxes, const int* __restrict__ toff,
+                                                   const BoxDev* __restrict__ boxes, const int* __restrict__ toff,
                                                    const int* __restrict__ tlist,
                                                    const PRec<typename StoreT<ST>::T>* __restrict__ rec,
                                                    double* __restrict__ out0, double* __restrict__ out1,
@@ -371,7 +436,7 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
     const int first = (G.order ? int(blockIdx.x) : xcd_tile(blockIdx.x, gridDim.x)) * G.tpb;
     const int last = min((long long)first + G.tpb, G.ntiles);
     for (int tile = first; tile < last; ++tile)
-        lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1, tin);
+        lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL, NPL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1, tin);
     if constexpr (COLL == 2)
         if (first == 0 && threadIdx.x == 0) *tout = *tin + 1;
 }
@@ -390,6 +455,20 @@ static void launch_step_c(const Geom& G, const void* src, void* dst, BoxDev* box
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
     const unsigned nb = (unsigned)((G.ntiles + G.tpb - 1) / G.tpb);
+    if constexpr (ST == ST_FP16) {
+        if (G.pairs) {
+            // two nodes per lane
+            if (ev0 && ev1)
+                hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 2>), dim3(nb), dim3(BLOCK / 2), 0,
+                                      s, ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist,
+                                      (const PRec<T>*)rec, out0, out1, tin, tout);
+            else
+                hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 2>), dim3(nb), dim3(BLOCK / 2), 0, s,
+                                   G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1, tin,
+                                   tout);
+            return;
+        }
+    }
     if (ev0 && ev1)
         hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s,
                               ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0,

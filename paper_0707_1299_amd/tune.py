@@ -45,10 +45,13 @@ ELEM_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "mom32": 4}
 
 def candidates(shape, storage="fp32"):
     nz, ny, nx = shape
-    big = nx * ny * nz * PLANES[storage] * ELEM_BYTES[storage] >= 4.0e9   # tiles under 64 wide need < 4 GiB boxes
+    # tiles with fewer than 64 lanes along x need boxes under 4 GiB; FP16 with nx even runs two
+    # nodes per lane
+    big = nx * ny * nz * PLANES[storage] * ELEM_BYTES[storage] >= 4.0e9
+    npl = 2 if storage == "fp16" and nx % 2 == 0 else 1
     out = []
     for t in TILES:
-        if t[0] > 2 * nx or (big and t[0] < 64):
+        if t[0] > 2 * nx or (big and t[0] // npl < 64):
             continue
         for v in VARIANTS:
             out.append((t, v))

@@ -54,11 +54,15 @@ def test_workspace_bytes_pure_and_monotone():
 
 @pytest.mark.parametrize("kw", [
     dict(shape=(3, 32, 32)), dict(shape=(32, 32, 2)), dict(nboxes=0), dict(storage=7),
-    dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=32), dict(variant=-1),
+    dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=64), dict(variant=-1),
     dict(storage="mom32", tile=(16, 8, 2)), dict(collision=3), dict(collision=-1),
     dict(collision="mrt", ghost_rate=0.0), dict(collision="mrt", ghost_rate=4.5),
     dict(storage="mom32", collision="bgk"), dict(storage="mom32", collision="mrt", ghost_rate=1.5),
     dict(kT=-1e-5), dict(kT=float("inf")), dict(storage="mom32", kT=1e-5),
+    # boxes of 4 GiB or more need at least 64 lanes along x (box-relative offsets are 32-bit)
+    dict(shape=(512, 512, 512), storage="fp32", tile=(32, 4, 2)),
+    dict(shape=(512, 512, 512), storage="fp16", tile=(64, 2, 2)),     # two nodes per lane: 32 lanes
+    dict(shape=(512, 512, 512), storage="fp16", tile=(32, 4, 2), variant=32),
 ])
 def test_bad_params_rejected(kw):
     args = dict(shape=(16, 16, 16), storage="fp32")
@@ -121,3 +125,12 @@ def test_copy_probe_rejects_bad_arguments_before_any_launch():
            ((1 << 20) + 32, 1 << 20, 64)]
     for s, d, n in bad:
         assert lib.lb_copy_probe(ctypes.c_void_p(s), ctypes.c_void_p(d), n, None) == lbm.LB_ERR_ARG, (s, d, n)
+
+
+@pytest.mark.parametrize("shape,storage,tile,variant", [
+    ((512, 512, 512), "fp16", (128, 2, 1), 0), ((512, 512, 512), "fp16", (64, 2, 2), 32),
+    ((512, 512, 512), "fp32", (64, 4, 1), 0), ((512, 512, 512), "fp16", None, 0), ((512, 512, 512), "fp32", None, 0),
+    ((256, 256, 256), "fp16", (64, 2, 2), 0)])
+def test_big_box_tiles_accepted(shape, storage, tile, variant):
+    """Whole-wave tile rows are accepted for boxes over 4 GiB (and the default tile is one)."""
+    assert lbm.lb_workspace_bytes(lbm.make_params(shape, storage, tile=tile, variant=variant)) > 0

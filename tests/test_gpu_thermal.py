@@ -193,3 +193,20 @@ def test_extra_noise_restores_stokes_einstein_for_radius_a():
     got = D * 6 * math.pi * eta / kT
     print("tracer + zeta': D 6 pi eta / kT = %.4f +- %.4f, 1/a = %.4f" % (got, dD * 6 * math.pi * eta / kT, inv_a))
     assert abs(got / inv_a - 1) < 0.06
+
+
+@pytest.mark.parametrize("shape", [(8, 6, 10), (6, 5, 9)])
+def test_fp16_thermal_step_matches_oracle(shape):
+    """Scaled FP16 storage with thermal noise: the scale exponent starts from the thermal amplitude
+    (no overflow at the first noisy step) and the trajectory follows the oracle's to the FP16 bar
+    (5e-3 of the largest velocity); nx = 10 runs two nodes per lane, nx = 9 one."""
+    tau, kT = 0.8, 1e-5
+    sets = _sets(shape, 4)
+    u, outs = gpu_run(shape, "fp16", tau, kT, 30, sets)
+    box = fluct.FluctBox(shape, tau, kT, SEED, sets=sets)
+    box.step(30)
+    _, uo = box.moments()
+    e, eU = rel(u, uo), rel(outs[0][1], box.sets[0]["U"])
+    print("thermal fp16 %s: u rel %.3e, U rel %.3e" % (shape, e, eU))
+    assert e <= 5e-3
+    assert eU <= 5e-3
