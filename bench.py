@@ -102,19 +102,20 @@ def make_inputs(kind, shape, n):
     return pos, frc, "colloid", dict(inv_a=1 / a, inv_aL=0.77)
 
 
-def tuned(shape, storage, nboxes=1):
+def tuned(shape, storage, nboxes=1, tag=None):
     from paper_0707_1299_amd import tune
-    return tune.lookup(shape, storage, nboxes) or (None, 0)
+    return tune.lookup(shape, storage, nboxes, tag) or (None, 0)
 
 
-def build_lattice(shape, storage, tau, kind, pos, frc, model, opts=None):
+def build_lattice(shape, storage, tau, kind, pos, frc, model, opts=None, name=None, choice=None):
+    """The workload's lattice and points; tile and variant from `choice` or the tuning cache."""
     import torch
     from paper_0707_1299_amd import lbm
     opts = opts or {}
     if kind == "boxes":
         w = pos
         nb = len(w["taus"])
-        tile, variant = tuned(shape, storage, nb)
+        tile, variant = choice or tuned(shape, storage, nb, name)
         lat = lbm.Lattice(shape, storage, nboxes=nb, tau=w["taus"], zero_net_force=True, max_points=len(w["pos"]),
                           tile=tile, variant=variant, **opts)
         p = torch.tensor(w["pos"], dtype=torch.float64, device="cuda")
@@ -123,7 +124,7 @@ def build_lattice(shape, storage, tau, kind, pos, frc, model, opts=None):
                              torch.tensor(w["box"], dtype=torch.int32, device="cuda"), lbm.LB_FORCES_STATIC,
                              lbm.PointModel(vel_sum=vsum))
         return lat, p
-    tile, variant = tuned(shape, storage)
+    tile, variant = choice or tuned(shape, storage, 1, name)
     if kind in ("droplets", "chains"):
         w = pos
         lat = lbm.Lattice(shape, storage, tau=tau, zero_net_force=(kind == "chains"), max_points=len(w["pos"]),
@@ -164,7 +165,7 @@ def traffic_from_profile(name, storage, N):
     if d.get("kernel_sha") != kernel_source_hash():
         return None
     shape = WORKLOADS[name][0]
-    tile, variant = tuned(shape, storage, WORKLOADS[name][4] if WORKLOADS[name][3] == "boxes" else 1)
+    tile, variant = tuned(shape, storage, WORKLOADS[name][4] if WORKLOADS[name][3] == "boxes" else 1, name)
     if list(tile or []) != d.get("tile") or variant != d.get("variant"):
         return None
     return d.get("bytes_per_launch")
@@ -227,7 +228,7 @@ def oracle_rates():
     return out
 
 
-def run_workload(name, steps, warmup, timing_steps, mlp=False):
+def run_workload(name, steps, warmup, timing_steps, mlp=False, choice=None):
     """Time one workload; returns (result dict, inputs) for the JSON line."""
     import torch
     shape, storage, tau, kind, n = WORKLOADS[name]
@@ -238,7 +239,7 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
         model = dict(model, mlp_seed=0)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(name))
+        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(name), name, choice)
         lat.step(warmup)
         lat.sync()
         torch.cuda.synchronize()
@@ -265,6 +266,24 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False):
     if kind in ("boxes", "droplets", "chains"):
         r["point_updates_per_s"] = npts * steps / elapsed
     return r, (shape, storage, tau, kind, n, pos, frc, fkind, model)
+
+
+def tune_workload(name, steps=40):
+    """Every candidate (tile, variant) of the tuner on this workload as it is timed (its points,
+    markers, collision options); the fastest whole step is cached under the workload's name."""
+    from paper_0707_1299_amd import tune
+    shape, storage, tau, kind, n = WORKLOADS[name]
+    nb = n if kind == "boxes" else 1
+    res = []
+    for tile, variant in tune.candidates(shape, storage):
+        r, _ = run_workload(name, steps, 10, max(5, steps // 2), choice=(tile, variant))
+        res.append(dict(tile=list(tile), variant=variant, kernel_ms=r["kernel_ms"], step_ms=r["ms_per_step"],
+                        GBs=r["achieved_GBs"]))
+        print("tile %-14s variant %2d  kernel %.4f ms  step %.4f ms" % (tile, variant, r["kernel_ms"], r["ms_per_step"]),
+              flush=True)
+    best = min(res, key=lambda e: e["step_ms"])
+    tune.save(shape, storage, nb, best, tag=name)
+    print(json.dumps(dict(best, workload=name)))
 
 
 def stream_copy_gbs(nbytes, reps=20):
@@ -315,6 +334,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=500)
     ap.add_argument("--all", action="store_true", help="also time the other workloads (reported under 'workloads')")
+    ap.add_argument("--tune", action="store_true",
+                    help="sweep tile x access variant on this workload and cache the fastest step under its name")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 10 device copies of 512 MiB (reference for the HBM byte counters)")
     a = ap.parse_args()
@@ -330,6 +351,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each": 1 << 29, "copies": 10, "kernels": ["torch copy_", "lb_copy_probe"]}))
         return
+    if a.tune:
+        tune_workload(a.workload)
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU decomposition "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
@@ -344,7 +368,7 @@ def main():
     copy_gbs, copy_same_gbs = stream_copy_gbs(1 << 30), stream_copy_gbs(same_bytes)
     shape, storage, tau, kind, n, pos, frc, fkind, model = inp
     traffic = traffic_from_profile(a.workload, storage, r["nodes"])
-    tile, variant = tuned(shape, storage)
+    tile, variant = tuned(shape, storage, 1, a.workload)
     out = {
         "metric": "MLUPS and % HBM roofline; colloid updates/s vs plain FP32 at stated error",
         "value": round(r["mlups"], 1),

@@ -85,7 +85,7 @@ def main():
     nboxes = bench.WORKLOADS[a.workload][4] if bench.WORKLOADS[a.workload][3] == "boxes" else 1
     alg = bench.BYTES_PER_NODE[storage] * shape[0] * shape[1] * shape[2] * nboxes
     traffic = (f * scale_f + w * scale_w) * 1024
-    tile, variant = bench.tuned(shape, storage, nboxes)
+    tile, variant = bench.tuned(shape, storage, nboxes, a.workload)
     out = dict(workload=a.workload, kernel=name, kernel_sha=bench.kernel_source_hash(),
                tile=list(tile) if tile else None, variant=variant,
                fetch_kib_per_dispatch=f, write_kib_per_dispatch=w, dispatches=len(kf[name]),

@@ -25,18 +25,29 @@ TILES = [(64, 2, 2), (64, 4, 1), (64, 1, 4), (128, 2, 1), (128, 1, 2), (256, 1, 
 VARIANTS = [0, 2, 4, 6, 8, 10, 16, 18, 20, 22]
 
 
-def key(shape, storage, nboxes):
+def key(shape, storage, nboxes, tag=None):
     nz, ny, nx = shape
-    return "%s/%s/%dx%dx%d/b%d" % (ARCH, storage, nx, ny, nz, nboxes)
+    k = "%s/%s/%dx%dx%d/b%d" % (ARCH, storage, nx, ny, nz, nboxes)
+    return k + "/" + tag if tag else k
 
 
-def lookup(shape, storage, nboxes=1):
+def lookup(shape, storage, nboxes=1, tag=None):
+    """(tile, variant) cached for this shape and storage; with a tag (a named workload, whose
+    points or collision options change the best choice) the tagged entry if there is one."""
     if not os.path.exists(CACHE):
         return None
-    d = json.load(open(CACHE)).get(key(shape, storage, nboxes))
+    c = json.load(open(CACHE))
+    d = (c.get(key(shape, storage, nboxes, tag)) if tag else None) or c.get(key(shape, storage, nboxes))
     if not d:
         return None
     return tuple(d["tile"]), int(d["variant"])
+
+
+def save(shape, storage, nboxes, entry, tag=None):
+    d = json.load(open(CACHE)) if os.path.exists(CACHE) else {}
+    d[key(shape, storage, nboxes, tag)] = entry
+    with open(CACHE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
 
 
 PLANES = {"fp64": 19, "fp32": 19, "fp16": 19, "mom32": 10}
@@ -51,9 +62,10 @@ def candidates(shape, storage="fp32"):
     npl = 2 if storage == "fp16" and nx % 2 == 0 else 1
     out = []
     for t in TILES:
-        if t[0] > 2 * nx or (big and t[0] // npl < 64):
-            continue
-        for v in VARIANTS:
+        for v in VARIANTS + ([v | 32 for v in VARIANTS] if npl == 2 else []):
+            lanes = t[0] // (1 if v & 32 else npl)        # bit 32: one FP16 node per lane
+            if t[0] > 2 * nx or (big and lanes < 64):
+                continue
             out.append((t, v))
     return out
 
@@ -121,11 +133,9 @@ def tune(shape, storage, nboxes=1, steps=100, points=None, save=True, verbose=Tr
                   flush=True)
     best = min(res, key=lambda r: r["step_ms"])
     if save:
-        d = json.load(open(CACHE)) if os.path.exists(CACHE) else {}
-        d[key(shape, storage, nboxes)] = dict(tile=best["tile"], variant=best["variant"], kernel_ms=best["kernel_ms"],
-                                              step_ms=best["step_ms"], GBs=best["GBs"])
-        with open(CACHE, "w") as f:
-            json.dump(d, f, indent=1, sort_keys=True)
+        globals()["save"](shape, storage, nboxes, dict(tile=best["tile"], variant=best["variant"],
+                                                       kernel_ms=best["kernel_ms"], step_ms=best["step_ms"],
+                                                       GBs=best["GBs"]))
     return best, res
 
 
