@@ -261,13 +261,48 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
     const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
     const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
-    const T base = drho - T(1.5) * (Bxx + Byy + Bzz);
+    T base = drho - T(1.5) * (Bxx + Byy + Bzz);
 
     // f*_i / w_i = base + c_i.(3A) + sum_a c_ia^2 (9/2) B_aa + sum_{a<b} c_ia c_ib 9 B_ab: for an
     // opposite pair the even part is shared and the odd part (3A.c_i) changes sign
     const T a3x = T(3) * ax, a3y = T(3) * ay, a3z = T(3) * az;
-    const T bxx = T(4.5) * Bxx, byy = T(4.5) * Byy, bzz = T(4.5) * Bzz;
-    const T bxy = T(9) * Bxy, bxz = T(9) * Bxz, byz = T(9) * Byz;
+    T bxx = T(4.5) * Bxx, byy = T(4.5) * Byy, bzz = T(4.5) * Bzz;
+    T bxy = T(9) * Bxy, bxz = T(9) * Bxz, byz = T(9) * Byz;
+
+    // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2), in
+    // units of w_i: amp[k] = phi_k / b_k.  Philox call j gives the normals of modes 4j .. 4j+3.
+    // The bulk and shear modes fold into the pieces above (stress_modes_fold); the ghosts are
+    // added per opposite pair after the rebuild, as an even and an odd part.
+    [[maybe_unused]] T amp[16];
+    [[maybe_unused]] uint32_t node = 0;
+    [[maybe_unused]] unsigned long long tstep = 0;
+    auto draw = [&](int j) {
+        const Philox4 q = node_draw(node, uint32_t(box), tstep, uint32_t(j), G.seed_lo, G.seed_hi);
+        T r[4];
+        box_muller<T>(q.v[0], q.v[1], r[0], r[1]);
+        box_muller<T>(q.v[2], q.v[3], r[2], r[3]);
+        const T sr = sqrt(rho);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int k = 4 * j + m;
+            if (k >= 15) continue;
+            const T nzk = T(k == 0 ? B.nz_b : (k < 6 ? B.nz_s : B.nz_g));
+            amp[k] = sr * nzk * T(1.0 / __builtin_sqrt(mode_norm(k))) * r[m];
+        }
+    };
+    if constexpr (COLL == 2 && ST != ST_MOM32) {
+        tstep = *tin;
+        node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(xh);
+        draw(0);
+        draw(1);
+        base -= amp[0];
+        bxx += amp[0] + T(2) * amp[1];
+        byy += amp[0] - amp[1] + amp[2];
+        bzz += amp[0] - amp[1] - amp[2];
+        bxy += amp[3];
+        bxz += amp[4];
+        byz += amp[5];
+    }
     constexpr bool GHOST = COLL && ST != ST_MOM32;
     // with the ghost part already in br: br + (ev +- od), the same sum as (ev +- od) + br
     br[0] = GHOST ? br[0] + base : base;
@@ -285,30 +320,23 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         br[i + 1] = GHOST ? br[i + 1] + (ev - od) : ev - od;
     }
     if constexpr (COLL == 2 && ST != ST_MOM32) {
-        // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2);
-        // added here in units of w_i
-        const unsigned long long t = *tin;
-        const uint32_t node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(xh);
-        const T sr = sqrt(rho);
-        // each call gives four normals for modes 4j .. 4j+3, applied at once (few live registers)
+        draw(2);
+        draw(3);
+        br[0] += amp[12];     // the only ghost that is non-zero at rest (e_12(0) = 1)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const Philox4 q = node_draw(node, uint32_t(box), t, uint32_t(j), G.seed_lo, G.seed_hi);
-            T r[4];
-            box_muller<T>(q.v[0], q.v[1], r[0], r[1]);
-            box_muller<T>(q.v[2], q.v[3], r[2], r[3]);
+        for (int i = 1; i < NQ; i += 2) {
+            T ev = 0, od = 0;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int k = 4 * j + m;
-                if (k >= 15) continue;
-                const T nzk = T(k == 0 ? B.nz_b : (k < 6 ? B.nz_s : B.nz_g));
-                const T amp = sr * nzk * T(1.0 / __builtin_sqrt(mode_norm(k))) * r[m];
-#pragma unroll
-                for (int i = 0; i < NQ; ++i) {
-                    const int e = emode(k, i);
-                    if (e != 0) br[i] += T(e) * amp;
-                }
+            for (int k = 6; k < 15; ++k) {
+                const int e = emode(k, i);
+                if (e == 0) continue;
+                if (mode_even(k))
+                    ev += T(e) * amp[k];
+                else
+                    od += T(e) * amp[k];
             }
+            br[i] += ev + od;
+            br[i + 1] += ev - od;
         }
     }
 

@@ -26,8 +26,10 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        // each 32 x 32 -> 64-bit product as one multiply (v_mad_u64_u32) giving both halves
+        const uint64_t p0 = uint64_t(c0) * 0xD2511F53u, p1 = uint64_t(c2) * 0xCD9E8D57u;
+        const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+        const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
         c0 = hi1 ^ c1 ^ k0;
         c1 = lo1;
         c2 = hi0 ^ c3 ^ k1;
@@ -83,6 +85,41 @@ __host__ __device__ constexpr int emode(int k, int i)
     default: return (2 * c2 - 3) * (y * y - z * z);
     }
 }
+
+// Parity under c -> -c: bulk, shear (0..5) and the ghosts 12..14 are even, the
+// ghosts 6..11 odd; velocities 2j+1 and 2j+2 are opposite, so e_k at the second
+// of a pair is +-e_k at the first.
+__host__ __device__ constexpr bool mode_even(int k) { return k < 6 || k >= 12; }
+
+constexpr bool modes_have_parity()
+{
+    for (int k = 0; k < 15; ++k)
+        for (int i = 1; i < NQ; i += 2)
+            if (emode(k, i + 1) != (mode_even(k) ? emode(k, i) : -emode(k, i))) return false;
+    for (int k = 0; k < 15; ++k)
+        if (!mode_even(k) && emode(k, 0) != 0) return false;
+    return true;
+}
+static_assert(modes_have_parity(), "mode parity table");
+
+// The bulk and shear modes are quadratic in c: sum_{k<6} e_k(c) a_k equals
+// -a0 + c_x^2 (a0 + 2 a1) + c_y^2 (a0 - a1 + a2) + c_z^2 (a0 - a1 - a2)
+//   + c_x c_y a3 + c_x c_z a4 + c_y c_z a5,
+// so their noise adds to the rest term and the second-moment pieces of the
+// post-collision bracket.  Checked on every velocity for unit amplitudes.
+constexpr bool stress_modes_fold()
+{
+    for (int k = 0; k < 6; ++k)
+        for (int i = 0; i < NQ; ++i) {
+            const int a[6] = {k == 0, k == 1, k == 2, k == 3, k == 4, k == 5};
+            const int x = cvel(i, 0), y = cvel(i, 1), z = cvel(i, 2);
+            const int folded = -a[0] + x * x * (a[0] + 2 * a[1]) + y * y * (a[0] - a[1] + a[2]) +
+                               z * z * (a[0] - a[1] - a[2]) + x * y * a[3] + x * z * a[4] + y * z * a[5];
+            if (folded != emode(k, i)) return false;
+        }
+    return true;
+}
+static_assert(stress_modes_fold(), "stress-mode noise folded into the bracket pieces");
 
 // b_k = sum_i w_i e_k(c_i)^2
 __host__ __device__ constexpr double mode_norm(int k)
