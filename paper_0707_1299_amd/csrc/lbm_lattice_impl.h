@@ -66,7 +66,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     t /= G.nty;
     const int itz = t % G.ntz;
     const int box = t / G.ntz;
-    // a tile at least one wave wide puts each wave on one row: y and z are then wave-uniform
+    // a tile row of at least 64 lanes puts each wave on one row: y and z are then wave-uniform
     // and live in scalar registers (so do the upstream row indices of the pull)
     const int tid_w = LX >= 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x)) : int(threadIdx.x);
     const int lx = threadIdx.x % LX, ly = (tid_w / LX) % TY, lz = tid_w / (LX * TY);
@@ -83,10 +83,9 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const S* sb = src + (long long)box * G.sbox;
 
     // ---- pull: population i at x comes from x - c_i
-    // Addressing (see load_pop): a tile at least one wave wide in x keeps each wave on
-    // one row; narrower tiles address from the box start (boxes under 4 GiB, checked at
-    // set-up); variant bit 0 uses 64-bit global addresses.  The planes of FP16 storage
-    // stay separate (row_layout), the others are interleaved per row.
+    // Addressing (see load_pop): a tile row of at least 64 lanes keeps each wave on one row;
+    // narrower tiles address from the box start (boxes under 4 GiB, checked at set-up);
+    // variant bit 0 uses 64-bit global addresses.
     constexpr bool WIDE = (VAR & 1);
     constexpr int ADDR = WIDE ? A_G64 : (LX >= 64 ? A_ROW : A_BOX32);
     // moment pieces are re-read by up to 18 neighbours: always cached loads
@@ -111,281 +110,282 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     T mx = 0;                     // FP16: largest |f*_i / w_i| of the lane's nodes
     T uxs[NPL], uys[NPL], uzs[NPL];
 
+    // ---- per node of the lane: moments, force, collision, post-collision values
 #pragma unroll
     for (int h = 0; h < NPL; ++h) {
-    const int xh = x + h;
-    if constexpr (NPL == 2) {
-        // FP16 value of node xh (low half: x, high half: x + 1), converted exactly, then weighted
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const uint32_t bits = h == 0 ? (wpair[i] & 0xffffu) : (wpair[i] >> 16);
-            f[i] = fp16_in(__builtin_bit_cast(_Float16, uint16_t(bits)), float(wgt(i)));
-        }
-    }
-
-    // ---- moments (10 values), over opposite pairs (i, i+1): the pair sum feeds the even
-    // moments (mass, second moments), the difference the odd ones (momentum)
-    T drho = f[0], jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
-#pragma unroll
-    for (int i = 1; i < NQ; i += 2) {
-        const T sm = f[i] + f[i + 1], df = f[i] - f[i + 1];
-        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-        drho += sm;
-        if (cx != 0) { jx += cx > 0 ? df : -df; pxx += sm; }
-        if (cy != 0) { jy += cy > 0 ? df : -df; pyy += sm; }
-        if (cz != 0) { jz += cz > 0 ? df : -df; pzz += sm; }
-        if (cx * cy != 0) pxy += cx * cy > 0 ? sm : -sm;
-        if (cx * cz != 0) pxz += cx * cz > 0 ? sm : -sm;
-        if (cy * cz != 0) pyz += cy * cz > 0 ? sm : -sm;
-    }
-    if constexpr (ST == ST_FP16) {
-        const T s = MODE == M_STEP ? T(B.s_in) : T(ldexpf(1.0f, -B.e_data));
-        drho *= s; jx *= s; jy *= s; jz *= s;
-        pxx *= s; pyy *= s; pzz *= s; pxy *= s; pxz *= s; pyz *= s;
-    }
-
-    // ---- force density at this node: counter-force + the tile's points
-    T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
-    if (h == 0 && toff) {
-        k0 = toff[tile];
-        k1 = toff[tile + 1];
-    }
-    for (int k = k0; k < k1; ++k) {
-        const PRec<T>& r = rec[pk_point(tlist[k])];
-        const T w = stencil_w<T>(xh, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
-                    stencil_w<T>(z, r.bz, G.nz, r.wz);
-        gx += r.f[0] * w;
-        gy += r.f[1] * w;
-        gz += r.f[2] * w;
-    }
-
-    const T rho = T(G.rho0) + drho;
-    const T ir = T(1) / rho;
-    const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
-
-    if constexpr (MODE == M_MOMENTS) {
-        if (valid) {
-            const long long n = ((long long)z * G.ny + y) * G.nx + x;
-            if (out0) out0[(long long)box * G.N + n] = G.rho0 + double(drho);
-            out1[((long long)box * 3 + 0) * G.N + n] = double(ux);
-            out1[((long long)box * 3 + 1) * G.N + n] = double(uy);
-            out1[((long long)box * 3 + 2) * G.N + n] = double(uz);
-        }
-        return;
-    }
-
-    if constexpr (MODE == M_DIAG) {
-        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + pxy + pxz + pyz + gx + gy + gz;
-        const bool bad = !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
-        double v[LBD_N];
-        const double X = x, Y = y, Z = z;
-        v[0] = drho; v[1] = jx; v[2] = jy; v[3] = jz;
-        v[4] = gx; v[5] = gy; v[6] = gz;
-        v[7] = Y * double(gz) - Z * double(gy);
-        v[8] = Z * double(gx) - X * double(gz);
-        v[9] = X * double(gy) - Y * double(gx);
-        v[10] = sqrt(double(ux) * ux + double(uy) * uy + double(uz) * uz);
-        v[11] = bad ? 1.0 : 0.0;
-        __shared__ double red[4][LBD_N];
-#pragma unroll
-        for (int c = 0; c < LBD_N; ++c) {
-            double a = valid ? v[c] : 0.0;
-            if (c == 10) {
-                if (!(a == a)) a = 0.0;  // max ignores NaN; the count reports it
-                a = wave_max(a);
-            } else {
-                a = wave_sum(a);
-            }
-            if (lane == 0) red[wave][c] = a;
-        }
-        __syncthreads();
-        if (threadIdx.x < LBD_N) {
-            const int c = threadIdx.x;
-            double a;
-            if (c == 10)
-                a = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
-            else
-                a = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-            out0[(long long)tile * LBD_N + c] = a;
-        }
-        return;
-    }
-
-    // ---- M_STEP: collide
-    const T ax = jx + gx, ay = jy + gy, az = jz + gz;
-    const T third = T(1.0 / 3.0);
-    const T sxx = pxx - drho * third, syy = pyy - drho * third, szz = pzz - drho * third;
-    T br[NQ];   // post-collision f*_i / w_i
-    if constexpr (COLL && ST != ST_MOM32) {
-        // ghost part of the pulled state (deviation minus its projection onto 1, c, Q),
-        // carried over with factor kappa_g, in units of w_i; taken first so that the pulled
-        // populations are dead before the collision
-        const T kg = T(B.kappa_g);
-        const T hbase = drho - T(1.5) * (sxx + syy + szz);
-        T s_in = T(1);
-        if constexpr (ST == ST_FP16) s_in = T(B.s_in);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-            T a = 0, q = 0;
-            if (cx != 0) { a += cx > 0 ? jx : -jx; q += sxx; }
-            if (cy != 0) { a += cy > 0 ? jy : -jy; q += syy; }
-            if (cz != 0) { a += cz > 0 ? jz : -jz; q += szz; }
-            if (cx * cy != 0) q += cx * cy > 0 ? T(2) * pxy : T(-2) * pxy;
-            if (cx * cz != 0) q += cx * cz > 0 ? T(2) * pxz : T(-2) * pxz;
-            if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
-            const T hb = hbase + T(3) * a + T(4.5) * q;
-            const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
-            br[i] = kg * (f[i] * s_in * inv_w - hb);
-        }
-    }
-    const T tau = T(B.tau), om = T(B.omega);
-    T Bxx, Byy, Bzz;
-    if constexpr (COLL) {
-        // shear drivers of the diagonal; their trace relaxes at omega_b instead (bulk mode)
-        const T dxx = sxx - rho * ux * ux - tau * (T(2) * ux * gx);
-        const T dyy = syy - rho * uy * uy - tau * (T(2) * uy * gy);
-        const T dzz = szz - rho * uz * uz - tau * (T(2) * uz * gz);
-        const T trs = (dxx + dyy + dzz) * third;
-        const T tb = T(B.tau_b), omb = T(B.omega_b);
-        const T trb = (sxx + syy + szz - rho * (ux * ux + uy * uy + uz * uz) -
-                       tb * (T(2) * (ux * gx + uy * gy + uz * gz))) * third;
-        Bxx = sxx - om * (dxx - trs) - omb * trb;
-        Byy = syy - om * (dyy - trs) - omb * trb;
-        Bzz = szz - om * (dzz - trs) - omb * trb;
-    } else {
-        Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
-        Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
-        Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
-    }
-    const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
-    const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
-    const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
-    T base = drho - T(1.5) * (Bxx + Byy + Bzz);
-
-    // f*_i / w_i = base + c_i.(3A) + sum_a c_ia^2 (9/2) B_aa + sum_{a<b} c_ia c_ib 9 B_ab: for an
-    // opposite pair the even part is shared and the odd part (3A.c_i) changes sign
-    const T a3x = T(3) * ax, a3y = T(3) * ay, a3z = T(3) * az;
-    T bxx = T(4.5) * Bxx, byy = T(4.5) * Byy, bzz = T(4.5) * Bzz;
-    T bxy = T(9) * Bxy, bxz = T(9) * Bxz, byz = T(9) * Byz;
-
-    // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2), in
-    // units of w_i: amp[k] = phi_k / b_k.  Philox call j gives the normals of modes 4j .. 4j+3.
-    // The bulk and shear modes fold into the pieces above (stress_modes_fold); the ghosts are
-    // added per opposite pair after the rebuild, as an even and an odd part.
-    [[maybe_unused]] T amp[16];
-    [[maybe_unused]] uint32_t node = 0;
-    [[maybe_unused]] unsigned long long tstep = 0;
-    auto draw = [&](int j) {
-        const Philox4 q = node_draw(node, uint32_t(box), tstep, uint32_t(j), G.seed_lo, G.seed_hi);
-        T r[4];
-        box_muller<T>(q.v[0], q.v[1], r[0], r[1]);
-        box_muller<T>(q.v[2], q.v[3], r[2], r[3]);
-        const T sr = sqrt(rho);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int k = 4 * j + m;
-            if (k >= 15) continue;
-            const T nzk = T(k == 0 ? B.nz_b : (k < 6 ? B.nz_s : B.nz_g));
-            amp[k] = sr * nzk * T(1.0 / __builtin_sqrt(mode_norm(k))) * r[m];
-        }
-    };
-    if constexpr (COLL == 2 && ST != ST_MOM32) {
-        tstep = *tin;
-        node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(xh);
-        draw(0);
-        draw(1);
-        base -= amp[0];
-        bxx += amp[0] + T(2) * amp[1];
-        byy += amp[0] - amp[1] + amp[2];
-        bzz += amp[0] - amp[1] - amp[2];
-        bxy += amp[3];
-        bxz += amp[4];
-        byz += amp[5];
-    }
-    constexpr bool GHOST = COLL && ST != ST_MOM32;
-    // with the ghost part already in br: br + (ev +- od), the same sum as (ev +- od) + br
-    br[0] = GHOST ? br[0] + base : base;
-#pragma unroll
-    for (int i = 1; i < NQ; i += 2) {
-        const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-        T ev = base, od = 0;
-        if (cx != 0) { od += cx > 0 ? a3x : -a3x; ev += bxx; }
-        if (cy != 0) { od += cy > 0 ? a3y : -a3y; ev += byy; }
-        if (cz != 0) { od += cz > 0 ? a3z : -a3z; ev += bzz; }
-        if (cx * cy != 0) ev += cx * cy > 0 ? bxy : -bxy;
-        if (cx * cz != 0) ev += cx * cz > 0 ? bxz : -bxz;
-        if (cy * cz != 0) ev += cy * cz > 0 ? byz : -byz;
-        br[i] = GHOST ? br[i] + (ev + od) : ev + od;
-        br[i + 1] = GHOST ? br[i + 1] + (ev - od) : ev - od;
-    }
-    if constexpr (COLL == 2 && ST != ST_MOM32) {
-        draw(2);
-        draw(3);
-        br[0] += amp[12];     // the only ghost that is non-zero at rest (e_12(0) = 1)
-#pragma unroll
-        for (int i = 1; i < NQ; i += 2) {
-            T ev = 0, od = 0;
-#pragma unroll
-            for (int k = 6; k < 15; ++k) {
-                const int e = emode(k, i);
-                if (e == 0) continue;
-                if (mode_even(k))
-                    ev += T(e) * amp[k];
-                else
-                    od += T(e) * amp[k];
-            }
-            br[i] += ev + od;
-            br[i + 1] += ev - od;
-        }
-    }
-
-    // ---- health of this node: non-finite moments or forces (checked before the stores so
-    // that nothing after them waits on the stores)
-    {
-        const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
-        bad = bad || (valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300)));
-    }
-
-    // ---- store the post-collision state of this node (two nodes per lane: packed below)
-    if constexpr (NPL == 2) {
-#pragma unroll
-        for (int i = 0; i < NQ; ++i) {
-            const uint32_t bits = __builtin_bit_cast(uint16_t, fp16_out(br[i], B.s_out));
-            opair[i] = h == 0 ? bits : (opair[i] | (bits << 16));
-        }
-    } else if (valid) {
-        if constexpr (ST == ST_MOM32) {
-            const T piece[MP_N] = {base, a3x, a3y, a3z, bxx, byy, bzz, bxy, bxz, byz};
-#pragma unroll
-            for (int k = 0; k < MP_N; ++k) store_pop<S, ADDR>(piece[k], db, G.rb, G.kp, box_bytes, k, row, x);
-        } else {
+        const int xh = x + h;
+        if constexpr (NPL == 2) {
+            // FP16 value of node xh (low half: x, high half: x + 1), converted exactly, then weighted
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
-                S v;
-                if constexpr (ST == ST_FP16)
-                    v = fp16_out(br[i], B.s_out);
-                else
-                    v = S(T(wgt(i)) * br[i]);
-                store_pop<S, ADDR>(v, db, G.rb, G.kp, box_bytes, i, row, x);
+                const uint32_t bits = h == 0 ? (wpair[i] & 0xffffu) : (wpair[i] >> 16);
+                f[i] = fp16_in(__builtin_bit_cast(_Float16, uint16_t(bits)), float(wgt(i)));
             }
         }
-    }
 
-    // ---- FP16: the largest stored magnitude, for the range check and the rescaling
-    if constexpr (ST == ST_FP16) {
+        // ---- moments (10 values), over opposite pairs (i, i+1): the pair sum feeds the even
+        // moments (mass, second moments), the difference the odd ones (momentum)
+        T drho = f[0], jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) mx = fmax(mx, fabs(br[i]));
-    }
-    uxs[h] = ux;
-    uys[h] = uy;
-    uzs[h] = uz;
+        for (int i = 1; i < NQ; i += 2) {
+            const T sm = f[i] + f[i + 1], df = f[i] - f[i + 1];
+            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+            drho += sm;
+            if (cx != 0) { jx += cx > 0 ? df : -df; pxx += sm; }
+            if (cy != 0) { jy += cy > 0 ? df : -df; pyy += sm; }
+            if (cz != 0) { jz += cz > 0 ? df : -df; pzz += sm; }
+            if (cx * cy != 0) pxy += cx * cy > 0 ? sm : -sm;
+            if (cx * cz != 0) pxz += cx * cz > 0 ? sm : -sm;
+            if (cy * cz != 0) pyz += cy * cz > 0 ? sm : -sm;
+        }
+        if constexpr (ST == ST_FP16) {
+            const T s = MODE == M_STEP ? T(B.s_in) : T(ldexpf(1.0f, -B.e_data));
+            drho *= s; jx *= s; jy *= s; jz *= s;
+            pxx *= s; pyy *= s; pzz *= s; pxy *= s; pxz *= s; pyz *= s;
+        }
+
+        // ---- force density at this node: counter-force + the tile's points
+        T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
+        if (h == 0 && toff) {
+            k0 = toff[tile];
+            k1 = toff[tile + 1];
+        }
+        for (int k = k0; k < k1; ++k) {
+            const PRec<T>& r = rec[pk_point(tlist[k])];
+            const T w = stencil_w<T>(xh, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
+                        stencil_w<T>(z, r.bz, G.nz, r.wz);
+            gx += r.f[0] * w;
+            gy += r.f[1] * w;
+            gz += r.f[2] * w;
+        }
+
+        const T rho = T(G.rho0) + drho;
+        const T ir = T(1) / rho;
+        const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
+
+        if constexpr (MODE == M_MOMENTS) {
+            if (valid) {
+                const long long n = ((long long)z * G.ny + y) * G.nx + x;
+                if (out0) out0[(long long)box * G.N + n] = G.rho0 + double(drho);
+                out1[((long long)box * 3 + 0) * G.N + n] = double(ux);
+                out1[((long long)box * 3 + 1) * G.N + n] = double(uy);
+                out1[((long long)box * 3 + 2) * G.N + n] = double(uz);
+            }
+            return;
+        }
+
+        if constexpr (MODE == M_DIAG) {
+            const T chk = drho + jx + jy + jz + pxx + pyy + pzz + pxy + pxz + pyz + gx + gy + gz;
+            const bool nonfin = !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300));
+            double v[LBD_N];
+            const double X = x, Y = y, Z = z;
+            v[0] = drho; v[1] = jx; v[2] = jy; v[3] = jz;
+            v[4] = gx; v[5] = gy; v[6] = gz;
+            v[7] = Y * double(gz) - Z * double(gy);
+            v[8] = Z * double(gx) - X * double(gz);
+            v[9] = X * double(gy) - Y * double(gx);
+            v[10] = sqrt(double(ux) * ux + double(uy) * uy + double(uz) * uz);
+            v[11] = nonfin ? 1.0 : 0.0;
+            __shared__ double red[4][LBD_N];
+#pragma unroll
+            for (int c = 0; c < LBD_N; ++c) {
+                double a = valid ? v[c] : 0.0;
+                if (c == 10) {
+                    if (!(a == a)) a = 0.0;  // max ignores NaN; the count reports it
+                    a = wave_max(a);
+                } else {
+                    a = wave_sum(a);
+                }
+                if (lane == 0) red[wave][c] = a;
+            }
+            __syncthreads();
+            if (threadIdx.x < LBD_N) {
+                const int c = threadIdx.x;
+                double a;
+                if (c == 10)
+                    a = fmax(fmax(red[0][c], red[1][c]), fmax(red[2][c], red[3][c]));
+                else
+                    a = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+                out0[(long long)tile * LBD_N + c] = a;
+            }
+            return;
+        }
+
+        // ---- M_STEP: collide
+        const T ax = jx + gx, ay = jy + gy, az = jz + gz;
+        const T third = T(1.0 / 3.0);
+        const T sxx = pxx - drho * third, syy = pyy - drho * third, szz = pzz - drho * third;
+        T br[NQ];   // post-collision f*_i / w_i
+        if constexpr (COLL && ST != ST_MOM32) {
+            // ghost part of the pulled state (deviation minus its projection onto 1, c, Q),
+            // carried over with factor kappa_g, in units of w_i; taken first so that the pulled
+            // populations are dead before the collision
+            const T kg = T(B.kappa_g);
+            const T hbase = drho - T(1.5) * (sxx + syy + szz);
+            T s_in = T(1);
+            if constexpr (ST == ST_FP16) s_in = T(B.s_in);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+                T a = 0, q = 0;
+                if (cx != 0) { a += cx > 0 ? jx : -jx; q += sxx; }
+                if (cy != 0) { a += cy > 0 ? jy : -jy; q += syy; }
+                if (cz != 0) { a += cz > 0 ? jz : -jz; q += szz; }
+                if (cx * cy != 0) q += cx * cy > 0 ? T(2) * pxy : T(-2) * pxy;
+                if (cx * cz != 0) q += cx * cz > 0 ? T(2) * pxz : T(-2) * pxz;
+                if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
+                const T hb = hbase + T(3) * a + T(4.5) * q;
+                const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
+                br[i] = kg * (f[i] * s_in * inv_w - hb);
+            }
+        }
+        const T tau = T(B.tau), om = T(B.omega);
+        T Bxx, Byy, Bzz;
+        if constexpr (COLL) {
+            // shear drivers of the diagonal; their trace relaxes at omega_b instead (bulk mode)
+            const T dxx = sxx - rho * ux * ux - tau * (T(2) * ux * gx);
+            const T dyy = syy - rho * uy * uy - tau * (T(2) * uy * gy);
+            const T dzz = szz - rho * uz * uz - tau * (T(2) * uz * gz);
+            const T trs = (dxx + dyy + dzz) * third;
+            const T tb = T(B.tau_b), omb = T(B.omega_b);
+            const T trb = (sxx + syy + szz - rho * (ux * ux + uy * uy + uz * uz) -
+                           tb * (T(2) * (ux * gx + uy * gy + uz * gz))) * third;
+            Bxx = sxx - om * (dxx - trs) - omb * trb;
+            Byy = syy - om * (dyy - trs) - omb * trb;
+            Bzz = szz - om * (dzz - trs) - omb * trb;
+        } else {
+            Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
+            Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
+            Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
+        }
+        const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
+        const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
+        const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
+        T base = drho - T(1.5) * (Bxx + Byy + Bzz);
+
+        // f*_i / w_i = base + c_i.(3A) + sum_a c_ia^2 (9/2) B_aa + sum_{a<b} c_ia c_ib 9 B_ab: for an
+        // opposite pair the even part is shared and the odd part (3A.c_i) changes sign
+        const T a3x = T(3) * ax, a3y = T(3) * ay, a3z = T(3) * az;
+        T bxx = T(4.5) * Bxx, byy = T(4.5) * Byy, bzz = T(4.5) * Bzz;
+        T bxy = T(9) * Bxy, bxz = T(9) * Bxz, byz = T(9) * Byz;
+
+        // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2), in
+        // units of w_i: amp[k] = phi_k / b_k.  Philox call j gives the normals of modes 4j .. 4j+3.
+        // The bulk and shear modes fold into the pieces above (stress_modes_fold); the ghosts are
+        // added per opposite pair after the rebuild, as an even and an odd part.
+        [[maybe_unused]] T amp[16];
+        [[maybe_unused]] uint32_t node = 0;
+        [[maybe_unused]] unsigned long long tstep = 0;
+        auto draw = [&](int j) {
+            const Philox4 q = node_draw(node, uint32_t(box), tstep, uint32_t(j), G.seed_lo, G.seed_hi);
+            T r[4];
+            box_muller<T>(q.v[0], q.v[1], r[0], r[1]);
+            box_muller<T>(q.v[2], q.v[3], r[2], r[3]);
+            const T sr = sqrt(rho);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int k = 4 * j + m;
+                if (k >= 15) continue;
+                const T nzk = T(k == 0 ? B.nz_b : (k < 6 ? B.nz_s : B.nz_g));
+                amp[k] = sr * nzk * T(1.0 / __builtin_sqrt(mode_norm(k))) * r[m];
+            }
+        };
+        if constexpr (COLL == 2 && ST != ST_MOM32) {
+            tstep = *tin;
+            node = (unsigned(z) * unsigned(G.ny) + unsigned(y)) * unsigned(G.nx) + unsigned(xh);
+            draw(0);
+            draw(1);
+            base -= amp[0];
+            bxx += amp[0] + T(2) * amp[1];
+            byy += amp[0] - amp[1] + amp[2];
+            bzz += amp[0] - amp[1] - amp[2];
+            bxy += amp[3];
+            bxz += amp[4];
+            byz += amp[5];
+        }
+        constexpr bool GHOST = COLL && ST != ST_MOM32;
+        // with the ghost part already in br: br + (ev +- od), the same sum as (ev +- od) + br
+        br[0] = GHOST ? br[0] + base : base;
+#pragma unroll
+        for (int i = 1; i < NQ; i += 2) {
+            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+            T ev = base, od = 0;
+            if (cx != 0) { od += cx > 0 ? a3x : -a3x; ev += bxx; }
+            if (cy != 0) { od += cy > 0 ? a3y : -a3y; ev += byy; }
+            if (cz != 0) { od += cz > 0 ? a3z : -a3z; ev += bzz; }
+            if (cx * cy != 0) ev += cx * cy > 0 ? bxy : -bxy;
+            if (cx * cz != 0) ev += cx * cz > 0 ? bxz : -bxz;
+            if (cy * cz != 0) ev += cy * cz > 0 ? byz : -byz;
+            br[i] = GHOST ? br[i] + (ev + od) : ev + od;
+            br[i + 1] = GHOST ? br[i + 1] + (ev - od) : ev - od;
+        }
+        if constexpr (COLL == 2 && ST != ST_MOM32) {
+            draw(2);
+            draw(3);
+            br[0] += amp[12];     // the only ghost that is non-zero at rest (e_12(0) = 1)
+#pragma unroll
+            for (int i = 1; i < NQ; i += 2) {
+                T ev = 0, od = 0;
+#pragma unroll
+                for (int k = 6; k < 15; ++k) {
+                    const int e = emode(k, i);
+                    if (e == 0) continue;
+                    if (mode_even(k))
+                        ev += T(e) * amp[k];
+                    else
+                        od += T(e) * amp[k];
+                }
+                br[i] += ev + od;
+                br[i + 1] += ev - od;
+            }
+        }
+
+        // ---- health of this node: non-finite moments or forces
+        {
+            const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
+            bad = bad || (valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300)));
+        }
+
+        // ---- store the post-collision state of this node (two nodes per lane: packed below)
+        if constexpr (NPL == 2) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                const uint32_t bits = __builtin_bit_cast(uint16_t, fp16_out(br[i], B.s_out));
+                opair[i] = h == 0 ? bits : (opair[i] | (bits << 16));
+            }
+        } else if (valid) {
+            if constexpr (ST == ST_MOM32) {
+                const T piece[MP_N] = {base, a3x, a3y, a3z, bxx, byy, bzz, bxy, bxz, byz};
+#pragma unroll
+                for (int k = 0; k < MP_N; ++k) store_pop<S, ADDR>(piece[k], db, G.rb, G.kp, box_bytes, k, row, x);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    S v;
+                    if constexpr (ST == ST_FP16)
+                        v = fp16_out(br[i], B.s_out);
+                    else
+                        v = S(T(wgt(i)) * br[i]);
+                    store_pop<S, ADDR>(v, db, G.rb, G.kp, box_bytes, i, row, x);
+                }
+            }
+        }
+
+        // ---- FP16: the largest stored magnitude, for the range check and the rescaling
+        if constexpr (ST == ST_FP16) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) mx = fmax(mx, fabs(br[i]));
+        }
+        uxs[h] = ux;
+        uys[h] = uy;
+        uzs[h] = uz;
     }   // nodes of the lane
 
     if constexpr (NPL == 2) {
         if (valid) {
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) store_pair<ADDR>(opair[i], reinterpret_cast<_Float16*>(db), G.rb, G.kp, box_bytes, i, row, x);
+            for (int i = 0; i < NQ; ++i)
+                store_pair<ADDR>(opair[i], reinterpret_cast<_Float16*>(db), G.rb, G.kp, box_bytes, i, row, x);
         }
     }
     if constexpr (ST == ST_FP16) {
