@@ -46,6 +46,9 @@ WORKLOADS = {
     "colloids256_thermal": ((256, 256, 256), "fp32", 0.5, "colloids", 10000),
     "droplets256": ((256, 256, 256), "fp32", 0.8, "droplets", 64),
     "chains256": ((256, 256, 256), "fp32", 0.8, "chains", 2048),
+    # one GPU's share of the 512^3 lattice split into 8 z-slabs (10^5 / 8 colloids), periodic in z
+    "slab512x512x64_fp32": ((64, 512, 512), "fp32", 0.5, "slab", 12500),
+    "slab512x512x64_fp16": ((64, 512, 512), "fp16", 0.5, "slab", 12500),
 }
 # lattice options of a workload: collision operator (default: the projected operator of
 # Eq. fiexp) and thermal noise
@@ -68,6 +71,8 @@ DESCR = {
                 "(R=12, 642 markers each, tension 1e-4): marker forces, spread, interpolate, move every step",
     "chains": "%d^3 periodic D3Q19 forced MRT, %s storage, tau=0.8, %d bead-spring chains of 32 markers "
               "(k=1e-3, l0=1, F_ext=-1e-6 z), counter-force on: marker forces, spread, interpolate, move every step",
+    "slab": "%dx%dx%d slab (one GPU's share of a 512^3 lattice in 8 z-slabs; periodic wrap in z standing in for "
+            "the halo exchange), %s storage, tau=1/2, %d sedimenting point colloids (a=0.684), counter-force on",
 }
 
 
@@ -96,6 +101,9 @@ def make_inputs(kind, shape, n):
         pos = workloads.chains(L, n, 32)
         ext = np.tile([0.0, 0.0, -1e-6], (len(pos), 1))
         return dict(pos=pos, ext=ext, chain_len=32, k=1e-3, l0=1.0), None, "chains", None
+    if kind == "slab":
+        pos, frc = workloads.colloids(shape[2], n, shape=shape)
+        return pos, frc, "colloid", dict(inv_a=1 / 0.684, inv_aL=0.77)
     pos, frc = workloads.colloids(L, n)
     # a = 0.117 (Table 1) at 256^3; a = 0.684 (volume fraction ~1e-3 with 10^5 colloids) at 512^3
     a = 0.684 if L >= 512 else 0.117
@@ -261,7 +269,7 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False, choice=None):
     r = dict(mlups=N * steps / elapsed / 1e6, ms_per_step=elapsed / steps * 1e3, kernel_ms=kavg_s * 1e3,
              achieved_GBs=achieved, frac=achieved / PEAK_HBM_GBS, nodes=N, points=int(npts), storage=storage,
              launches_timed=nlaunch, steps=steps)
-    if kind in ("colloid", "colloids"):
+    if kind in ("colloid", "colloids", "slab"):
         r["colloid_updates_per_s"] = n * steps / elapsed
     if kind in ("boxes", "droplets", "chains"):
         r["point_updates_per_s"] = npts * steps / elapsed
@@ -317,6 +325,8 @@ def describe(name, r):
         d = DESCR[kind] % (shape[0], storage, n, r["points"])
     elif kind == "boxes":
         d = DESCR[kind] % (n, shape[0], storage, r["points"])
+    elif kind == "slab":
+        d = DESCR[kind] % (shape[2], shape[1], shape[0], storage, n)
     else:
         d = DESCR[kind] % (shape[0], storage, n)
     c = OPTS.get(name)
@@ -383,7 +393,7 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32", "mom32": "f32"}[storage],
         "data": "synthetic",
         "config": {"workload": describe(a.workload, r), "nodes": r["nodes"], "points": r["points"],
-                   "seed": 20261200 + {"singularities": 2, "colloids": 3, "boxes": 4, "droplets": 5, "chains": 6}[kind],
+                   "seed": 20261200 + {"singularities": 2, "colloids": 3, "slab": 3, "boxes": 4, "droplets": 5, "chains": 6}[kind],
                    "tile": list(tile or ()), "variant": variant},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r["frac"], 4), "traffic": traffic,
@@ -397,7 +407,7 @@ def main():
     if "colloid_updates_per_s" in r:
         out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)
 
-    if not a.no_cpu and kind in ("singularities", "colloids") and a.workload not in OPTS:
+    if not a.no_cpu and kind in ("singularities", "colloids", "slab") and a.workload not in OPTS:
         box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
         out["cpu_baseline"] = cb
         # same number of steps on a fresh GPU lattice: error of this storage against the oracle
@@ -422,7 +432,8 @@ def main():
                                  ("singularities128_bgk", 2000, False), ("singularities128_mrt", 2000, False),
                                  ("singularities128_fp16_bgk", 2000, False), ("singularities128_thermal", 2000, False),
                                  ("colloids256_thermal", 300, False), ("droplets256", 300, False),
-                                 ("chains256", 300, False)):
+                                 ("chains256", 300, False), ("slab512x512x64_fp32", 300, False),
+                                 ("slab512x512x64_fp16", 300, False)):
             rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
             rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
             extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)

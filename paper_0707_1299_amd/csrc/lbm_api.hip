@@ -30,12 +30,14 @@ size_t storage_bytes(int st) { return st == LB_STORAGE_FP64 ? 8 : (st == LB_STOR
 
 size_t rec_bytes(int st) { return st == LB_STORAGE_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>); }
 
+// most tiles of extent t met by the binning window of a point (5 consecutive nodes, periodic)
 int max_axis_tiles(int n, int t)
 {
+    constexpr int WIN = 5;
     int best = 0;
     for (int b = 0; b < n; ++b) {
-        int seen[4], cnt = 0;
-        for (int k = 0; k < 4; ++k) {
+        int seen[WIN], cnt = 0;
+        for (int k = 0; k < WIN; ++k) {
             const int tile = ((b + k) % n) / t;
             bool dup = false;
             for (int j = 0; j < cnt; ++j) dup |= seen[j] == tile;
@@ -47,8 +49,8 @@ int max_axis_tiles(int n, int t)
 }
 
 struct Layout {
-    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, tlist_tmp, pslot, partial, fpart, pmax, tmax, ticket, tctr,
-        err, nf,
+    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, tlist_tmp, partial, fpart, pmax, tmax, ticket, tctr,
+        err, nf, rebin, win,
         diag, diagout;
     size_t total;
 };
@@ -168,7 +170,6 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.bsum = take(sizeof(int) * scan_blocks(G.ntiles));
     L.tlist = take(sizeof(int) * P.cap * G.maxp);
     L.tlist_tmp = take(sizeof(int) * P.cap * G.maxp);
-    L.pslot = take(sizeof(int) * P.cap * G.maxp);
     L.partial = take(sizeof(double) * 3 * P.cap * G.maxp);
     L.fpart = take(sizeof(double) * 3 * p->nboxes * P.chunks);
     L.pmax = take(sizeof(float) * p->nboxes * P.chunks);
@@ -177,6 +178,8 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.tctr = take(2 * sizeof(unsigned long long));
     L.err = take(sizeof(int) * 4);
     L.nf = take(sizeof(int) * p->nboxes);
+    L.rebin = take(sizeof(int));
+    L.win = take(sizeof(int4) * P.cap);
     L.diag = take(sizeof(double) * LBD_N * G.ntiles);
     L.diagout = take(sizeof(double) * LBD_N * p->nboxes);
     L.total = o;
@@ -216,6 +219,7 @@ struct lb_ctx {
     int cur;
     std::vector<Set> sets;
     unsigned long long gen;
+    unsigned long long binned_gen;   // gen the tile lists were last forced to rebuild for
     bool bins_valid;
     bool gc_valid;   // counter-force sums current for the registered static sets
     std::vector<GraphEntry> graphs;
@@ -237,7 +241,6 @@ struct lb_ctx {
     int* bsum() const { return (int*)(ws + P.L.bsum); }
     int* tlist() const { return (int*)(ws + P.L.tlist); }
     int* tlist_tmp() const { return (int*)(ws + P.L.tlist_tmp); }
-    int* pslot() const { return (int*)(ws + P.L.pslot); }
     double* partial() const { return (double*)(ws + P.L.partial); }
     double* fpart() const { return (double*)(ws + P.L.fpart); }
     float* pmax() const { return (float*)(ws + P.L.pmax); }
@@ -246,6 +249,8 @@ struct lb_ctx {
     unsigned long long* tctr() const { return (unsigned long long*)(ws + P.L.tctr); }
     int* errw() const { return (int*)(ws + P.L.err); }
     int* nf() const { return (int*)(ws + P.L.nf); }
+    int* rebin() const { return (int*)(ws + P.L.rebin); }
+    int4* win() const { return (int4*)(ws + P.L.win); }
     double* diag() const { return (double*)(ws + P.L.diag); }
     double* diagout() const { return (double*)(ws + P.L.diagout); }
 };
@@ -287,18 +292,28 @@ bool has_kind(const lb_ctx* c, int kind)
     return false;
 }
 
-// records + tile bins for the current point positions
+// After the sets change, the next list build must run whatever the positions:
+// raise the rebuild flag once per change.  Enqueued eagerly, never into a
+// captured graph (a graph replays every node it holds).
+void force_rebin(lb_ctx* c, hipStream_t s)
+{
+    if (c->binned_gen == c->gen) return;
+    launch_fill_u32(c->rebin(), 1, 1u, s);
+    c->binned_gen = c->gen;
+}
+
+// records + tile bins for the current point positions (the binning kernels
+// rebuild the lists only while the rebuild flag is set)
 void build_points(lb_ctx* c, hipStream_t s)
 {
     const Geom& G = c->P.G;
     long long off = 0;
     for (auto& st : c->sets) {
-        launch_prep(c->p.storage, G, st.n, off, st.pos, st.frc, st.box, c->rec(), c->count(), c->pslot(), c->errw(),
-                    s);
+        launch_prep(c->p.storage, G, st.n, off, st.pos, st.frc, st.box, c->rec(), c->errw(), s);
         off += st.n;
     }
     launch_bins(c->p.storage, G, off, c->rec(), c->count(), c->bsum(), c->toff(), c->cursor(), c->tlist(),
-                c->tlist_tmp(), c->pslot(), s);
+                c->tlist_tmp(), s);
     c->gc_valid = false;
 }
 
@@ -391,7 +406,7 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
                 }
                 a.out_scale = st.model.out_scale;
             }
-            launch_advect(G, a, c->boxes(), c->pslot(), c->partial(), s);
+            launch_advect(G, a, c->boxes(), c->partial(), s);
         }
         off += st.n;
     }
@@ -486,10 +501,13 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->P = P;
     c->ws = (char*)d_workspace;
     c->P.G.nf = c->nf();
+    c->P.G.rebin = c->rebin();
+    c->P.G.win = c->win();
     c->stream = (hipStream_t)hip_stream;
     c->cap_stream = nullptr;
     c->cur = 0;
     c->gen = 1;
+    c->binned_gen = 0;
     c->bins_valid = false;
     c->gc_valid = false;
     c->timing = false;
@@ -543,6 +561,8 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     launch_fill_u32(c->tmax(), G.ntiles, 0u, s);
     launch_fill_u32(c->errw(), 4, 0u, s);
     launch_fill_u32(c->nf(), p->nboxes, 0u, s);
+    launch_fill_u32(c->rebin(), 1, 1u, s);
+    launch_fill_u32(c->win(), 4 * c->P.cap, 0u, s);
     r = hip_check(c, hipMemcpyAsync(c->boxes(), c->hboxes.data(), sizeof(BoxDev) * p->nboxes, hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");
     if (!r) r = check_async(c);
@@ -658,6 +678,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
     if (nsteps < 0) return fail(c, LB_ERR_ARG, "nsteps < 0");
     if (nsteps == 0) return LB_OK;
     int left = nsteps;
+    force_rebin(c, c->stream);
     if (has_kind(c, LB_FORCES_NEXT_STEP)) {
         enqueue_step(c, c->stream, true);
         c->sets.erase(std::remove_if(c->sets.begin(), c->sets.end(),
@@ -668,6 +689,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
         c->gc_valid = false;
         c->steps++;
         left--;
+        force_rebin(c, c->stream);
     }
     const bool moving = has_kind(c, LB_COLLOIDS) || has_kind(c, KIND_ELASTIC);
     const bool pts = total_points(c) > 0;
@@ -696,6 +718,7 @@ int lb_step(lb_ctx* c, int32_t nsteps)
 static int prepare_fields(lb_ctx* c)
 {
     if (total_points(c) > 0) {
+        force_rebin(c, c->stream);
         elastic_forces(c, c->stream);
         build_points(c, c->stream);
         if (!has_kind(c, LB_COLLOIDS) && !has_kind(c, KIND_ELASTIC)) c->bins_valid = true;

@@ -424,7 +424,8 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
         const int x0 = itx * TX, y0 = ity * TY, z0 = itz * TZ;
         for (int kk = k0 + wave; kk < k1; kk += NW) {
-            const PRec<T>& r = rec[pk_point(tlist[kk])];
+            const int ent = tlist[kk];
+            const PRec<T>& r = rec[pk_point(ent)];
             int gx = r.bx + dx, gy = r.by + dy, gz = r.bz + dz;
             if (gx >= G.nx) gx -= G.nx;
             if (gy >= G.ny) gy -= G.ny;
@@ -437,9 +438,11 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             const T sy = wave_sum(su[1][li] * w);
             const T sz = wave_sum(su[2][li] * w);
             if (lane == 0) {
-                out0[(long long)kk * 3 + 0] = double(sx);
-                out0[(long long)kk * 3 + 1] = double(sy);
-                out0[(long long)kk * 3 + 2] = double(sz);
+                // the point's partial for this tile, in its own slot (point-major layout)
+                double* o = out0 + ((long long)pk_point(ent) * G.maxp + pk_slot(ent)) * 3;
+                o[0] = double(sx);
+                o[1] = double(sy);
+                o[2] = double(sz);
             }
         }
         __syncthreads();   // su is rewritten by the block's next tile
@@ -467,6 +470,10 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
         lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL, NPL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1, tin);
     if constexpr (COLL == 2)
         if (first == 0 && threadIdx.x == 0) *tout = *tin + 1;
+    // the tile lists of this step were current; the next step's records raise the flag again
+    // if a point leaves its window
+    if constexpr (MODE == M_STEP)
+        if (first == 0 && threadIdx.x == 0) *G.rebin = 0;
 }
 
 

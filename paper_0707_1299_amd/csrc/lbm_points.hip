@@ -15,13 +15,23 @@
 
 namespace lbm {
 
-// Distinct tiles met by the 4 consecutive nodes base .. base+3 (periodic) of
+// Binning window: a point is binned to the tiles met by WIN = 5 consecutive nodes
+// per axis, starting at its window base.  The 4-node Peskin stencil of the point
+// (base floor(R) - 1) lies in the window while base - window base is 0 or 1
+// (periodic), so the tile lists stay valid as the point moves, until a stencil
+// leaves its window ("skin crossing"); only then are the lists rebuilt.  The
+// window base is chosen when binning so that the point can move at least half a
+// node either way first: one node below the stencil base when the point sits in
+// the lower half of its cell, at the stencil base otherwise.
+constexpr int WIN = 5;
+
+// Distinct tiles met by the WIN consecutive nodes base .. base+WIN-1 (periodic) of
 // one axis, in order of first appearance.
-__device__ __forceinline__ int axis_tiles(int base, int n, int tdim, int (&out)[4])
+__device__ __forceinline__ int axis_tiles(int base, int n, int tdim, int (&out)[WIN])
 {
     int cnt = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < WIN; ++k) {
         int node = base + k;
         if (node >= n) node -= n;
         const int t = node / tdim;
@@ -32,16 +42,54 @@ __device__ __forceinline__ int axis_tiles(int base, int n, int tdim, int (&out)[
     return cnt;
 }
 
+// number of distinct tiles met by the window (as axis_tiles, without the list: every index
+// is known at compile time, so nothing goes to scratch memory)
+__device__ __forceinline__ int axis_count(int base, int n, int tdim)
+{
+    int t[WIN];
+#pragma unroll
+    for (int k = 0; k < WIN; ++k) {
+        int node = base + k;
+        if (node >= n) node -= n;
+        t[k] = node / tdim;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < WIN; ++k) {
+        bool dup = false;
+#pragma unroll
+        for (int j = 0; j < k; ++j) dup |= (t[j] == t[k]);
+        cnt += dup ? 0 : 1;
+    }
+    return cnt;
+}
+
 struct TileSet {
-    int tx[4], ty[4], tz[4];
+    int tx[WIN], ty[WIN], tz[WIN];
     int cx, cy, cz;
 };
 
-__device__ __forceinline__ void point_tiles(const Geom& G, int bx, int by, int bz, TileSet& s)
+// tiles of the window with bases (wx, wy, wz)
+__device__ __forceinline__ void window_tiles(const Geom& G, int wx, int wy, int wz, TileSet& s)
 {
-    s.cx = axis_tiles(bx, G.nx, G.tx, s.tx);
-    s.cy = axis_tiles(by, G.ny, G.ty, s.ty);
-    s.cz = axis_tiles(bz, G.nz, G.tz, s.tz);
+    s.cx = axis_tiles(wx, G.nx, G.tx, s.tx);
+    s.cy = axis_tiles(wy, G.ny, G.ty, s.ty);
+    s.cz = axis_tiles(wz, G.nz, G.tz, s.tz);
+}
+
+// window base of one axis for a point with stencil base b (wrapped) and 1-D weights w:
+// w[0] > w[3] exactly when the point lies in the lower half of its cell
+template <class T> __device__ __forceinline__ int window_base(int b, int n, const T (&w)[4])
+{
+    return w[0] > w[3] ? (b == 0 ? n - 1 : b - 1) : b;
+}
+
+// the stencil (base b) still lies in the window (base w0) of a periodic axis of length n
+__device__ __forceinline__ bool in_window(int b, int w0, int n)
+{
+    int d = b - w0;
+    if (d < 0) d += n;
+    return d <= WIN - 4;
 }
 
 __device__ __forceinline__ long long tile_id(const Geom& G, int box, int tz, int ty, int tx)
@@ -49,14 +97,39 @@ __device__ __forceinline__ long long tile_id(const Geom& G, int box, int tz, int
     return (((long long)box * G.ntz + tz) * G.nty + ty) * G.ntx + tx;
 }
 
+__device__ __forceinline__ int pick(const int (&a)[WIN], int j)
+{
+    int v = a[0];
+#pragma unroll
+    for (int q = 1; q < WIN; ++q) v = j == q ? a[q] : v;
+    return v;
+}
+
+// Tile of slot k of a point (k = (iz cy + iy) cx + ix over its distinct window tiles per
+// axis), or -1 past the point's last slot.
+__device__ __forceinline__ long long slot_tile(const Geom& G, const TileSet& s, int box, int k)
+{
+    if (k >= s.cx * s.cy * s.cz) return -1;
+    const int ix = k % s.cx, iy = (k / s.cx) % s.cy, iz = k / (s.cx * s.cy);
+    return tile_id(G, box, pick(s.tz, iz), pick(s.ty, iy), pick(s.tx, ix));
+}
+
+// The (point, slot) kernels run a group of lanes_per_point(maxp) consecutive lanes per point,
+// lane k of the group taking slot k: the atomics of one point then run side by side.
+int lanes_per_point(int maxp)
+{
+    int g = 1;
+    while (g < maxp) g <<= 1;
+    return g;
+}
+
 // ---------------------------------------------------------------------------
-// 1. records: wrapped base node, one-dimensional weights, force; count the
-//    (tile, point) pairs.  err bit 1: box id out of range, bit 2: non-finite input.
+// 1. records: wrapped base node, one-dimensional weights, force (one thread per
+//    point).  err bit 1: box id out of range, bit 2: non-finite input.
 template <class T>
 __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long long off, const double* __restrict__ pos,
                                               const double* __restrict__ frc, const int* __restrict__ boxid,
-                                              PRec<T>* __restrict__ rec, int* __restrict__ count,
-                                              int* __restrict__ pslot, int* __restrict__ err)
+                                              PRec<T>* __restrict__ rec, int* __restrict__ err)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -86,7 +159,7 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
         peskin4(x - b0, w);
         base[a] = b0 == 0 ? L[a] - 1 : b0 - 1;
         T* dst = a == 0 ? r.wx : (a == 1 ? r.wy : r.wz);
-        for (int k = 0; k < 4; ++k) dst[k] = T(w[k]);
+        for (int q = 0; q < 4; ++q) dst[q] = T(w[q]);
     }
     r.bx = base[0];
     r.by = base[1];
@@ -97,12 +170,33 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
     r.f[2] = T(F[2]);
     r.pad = T(0);
     rec[p] = r;
-    for (int k = 0; k < G.maxp; ++k) pslot[p * G.maxp + k] = -1;
+    // skin crossing: the stencil has left the window it was binned with
+    const int4 w = G.win[p];
+    if (!(in_window(r.bx, w.x, G.nx) && in_window(r.by, w.y, G.ny) && in_window(r.bz, w.z, G.nz) && w.w == box))
+        atomicOr(G.rebin, 1);
+}
+
+// 1b. (only when the lists are rebuilt) choose each point's window and count the
+//    (tile, point) pairs: one group of gp lanes per point (see lanes_per_point),
+//    lane 0 storing the window, lane k counting the point in the tile of slot k.
+template <class T>
+__global__ __launch_bounds__(256) void k_count(const Geom G, long long n, long long off, int gp,
+                                               const PRec<T>* __restrict__ rec, int* __restrict__ count)
+{
+    if (!*G.rebin) return;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = gid / gp;
+    const int k = int(gid % gp);
+    if (i >= n || k >= G.maxp) return;
+    const long long p = off + i;
+    const PRec<T> r = rec[p];
+    const int4 w = make_int4(window_base(r.bx, G.nx, r.wx), window_base(r.by, G.ny, r.wy),
+                             window_base(r.bz, G.nz, r.wz), r.box);
+    if (k == 0) G.win[p] = w;
     TileSet s;
-    point_tiles(G, r.bx, r.by, r.bz, s);
-    for (int iz = 0; iz < s.cz; ++iz)
-        for (int iy = 0; iy < s.cy; ++iy)
-            for (int ix = 0; ix < s.cx; ++ix) atomicAdd(&count[tile_id(G, box, s.tz[iz], s.ty[iy], s.tx[ix])], 1);
+    window_tiles(G, w.x, w.y, w.z, s);
+    const long long t = slot_tile(G, s, r.box, k);
+    if (t >= 0) atomicAdd(&count[t], 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -139,8 +233,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total)
     return r;
 }
 
-__global__ __launch_bounds__(SCAN_B) void k_scan_sums(long long n, const int* __restrict__ count, int* __restrict__ bsum)
+__global__ __launch_bounds__(SCAN_B) void k_scan_sums(long long n, const int* __restrict__ count, int* __restrict__ bsum,
+                                                      const int* __restrict__ rebin)
 {
+    if (!*rebin) return;
     __shared__ int sh[SCAN_B / 64 + 1];
     const long long i = (long long)blockIdx.x * SCAN_B + threadIdx.x;
     const int v = i < n ? count[i] : 0;
@@ -150,8 +246,10 @@ __global__ __launch_bounds__(SCAN_B) void k_scan_sums(long long n, const int* __
 }
 
 __global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restrict__ count, const int* __restrict__ bsum,
-                                                       int* __restrict__ toff, int* __restrict__ cursor)
+                                                       int* __restrict__ toff, int* __restrict__ cursor,
+                                                       const int* __restrict__ rebin)
 {
+    if (!*rebin) return;
     __shared__ int sh[SCAN_B / 64 + 1];
     __shared__ int pre;
     // prefix of the block sums before this block
@@ -175,46 +273,45 @@ __global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restr
 }
 
 // ---------------------------------------------------------------------------
-// 3. fill the per-tile point lists (slot order from atomics; fixed by step 4)
-template <class T>
-__global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, const PRec<T>* __restrict__ rec,
-                                              const int* __restrict__ toff, int* __restrict__ cursor,
-                                              int* __restrict__ tlist)
+// 3. fill the per-tile point lists (slot order from atomics; fixed by step 4),
+//    one lane per (point, slot) as in step 1b.
+__global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int gp, const int* __restrict__ toff,
+                                              int* __restrict__ cursor, int* __restrict__ tlist)
 {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!*G.rebin) return;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long p = gid / gp;
+    const int k = int(gid % gp);
     if (p >= npts) return;
-    const PRec<T> r = rec[p];
+    const int4 w = G.win[p];
     TileSet s;
-    point_tiles(G, r.bx, r.by, r.bz, s);
-    for (int iz = 0; iz < s.cz; ++iz)
-        for (int iy = 0; iy < s.cy; ++iy)
-            for (int ix = 0; ix < s.cx; ++ix) {
-                const long long t = tile_id(G, r.box, s.tz[iz], s.ty[iy], s.tx[ix]);
-                const int slot = toff[t] + atomicAdd(&cursor[t], 1);
-                tlist[slot] = int(p << PK_BITS) | ((iz * s.cy + iy) * s.cx + ix);
-            }
+    window_tiles(G, w.x, w.y, w.z, s);
+    const long long t = slot_tile(G, s, w.w, k);
+    if (t < 0) return;
+    const int slot = toff[t] + atomicAdd(&cursor[t], 1);
+    tlist[slot] = int(p << PK_BITS) | k;
 }
 
-// 4. sort every tile's list by point index (so sums run in a fixed order) and
-//    record, for each point and each tile it touches, where it sits in that
-//    tile's list.  One wave per tile: each entry's position is the number of
-//    smaller entries in the same list (entries are distinct), so a crowded
-//    tile costs k^2 / 64 compares per lane instead of a serial k^2 sort.
-__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, const int* __restrict__ toff,
-                                                    const int* __restrict__ tin, int* __restrict__ tout,
-                                                    int* __restrict__ pslot)
+// 4. sort every tile's list by point index (so sums run in a fixed order).  One
+//    thread per list entry: its position is the number of smaller entries in the
+//    same list (entries are distinct), found by a scan of that list; empty tiles
+//    cost nothing.
+__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_entries, const int* __restrict__ toff,
+                                                    const int* __restrict__ tin, int* __restrict__ tout)
 {
-    const long long t = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (t >= G.ntiles) return;
-    const int lane = threadIdx.x & 63;
+    if (!*G.rebin) return;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= max_entries || e >= toff[G.ntiles]) return;
+    const int v = tin[e];
+    const int p = pk_point(v), k = pk_slot(v);
+    const int4 w = G.win[p];
+    TileSet s;
+    window_tiles(G, w.x, w.y, w.z, s);
+    const long long t = slot_tile(G, s, w.w, k);
     const int a = toff[t], b = toff[t + 1];
-    for (int i = a + lane; i < b; i += 64) {
-        const int v = tin[i];
-        int rank = 0;
-        for (int j = a; j < b; ++j) rank += tin[j] < v ? 1 : 0;
-        tout[a + rank] = v;
-        pslot[(long long)pk_point(v) * G.maxp + pk_slot(v)] = a + rank;
-    }
+    int rank = 0;
+    for (int j = a; j < b; ++j) rank += tin[j] < v ? 1 : 0;
+    tout[a + rank] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -315,7 +412,12 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
 // ---------------------------------------------------------------------------
 // 6. interpolated velocity of each point (sum of its tile partials in a fixed
 //    order), optional outputs, and the colloid update with the optional MLP
-//    correction to 1/a_L.
+//    correction to 1/a_L.  A group of ADV_GP lanes per point: lane r of the group
+//    sums slots r, r + ADV_GP, ... (all its loads in flight at once), a butterfly
+//    over the group adds the lanes' sums (every lane ends with the same bits, as
+//    a + b == b + a), and lane 0 of the group finishes the point.
+constexpr int ADV_GP = 8;
+static_assert((64 / ADV_GP) * ADV_GP >= (1 << PK_BITS), "a group covers every slot a point can have");
 struct AdvectArgs {
     long long n, off;
     const double* frc;
@@ -360,25 +462,37 @@ __device__ float mlp_eval(const float* __restrict__ W, const float (&xin)[4])
 }
 
 __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
-                                                const int* __restrict__ pslot, const double* __restrict__ partial)
+                                                const double* __restrict__ partial)
 {
     __shared__ float W[LBML_NPARAM_DEV];
     if (A.mlp) {
         for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) W[k] = bf16_to_f32(A.mlp[k]);
         __syncthreads();
     }
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = gid / ADV_GP;
+    const int r = int(gid % ADV_GP);
+    if (i >= A.n) return;   // whole groups: a group is 8 aligned lanes of one wave
     const long long p = A.off + i;
+    // the point's partials, one per tile of its window (nt <= maxp <= 64 slots)
+    const int4 win = G.win[p];
+    const int nt = axis_count(win.x, G.nx, G.tx) * axis_count(win.y, G.ny, G.ty) * axis_count(win.z, G.nz, G.tz);
+    const double* pp = partial + p * G.maxp * 3;
+    double v[64 / ADV_GP][3];
+#pragma unroll
+    for (int m = 0; m < 64 / ADV_GP; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[m][c] = r + m * ADV_GP < nt ? pp[(r + m * ADV_GP) * 3 + c] : 0.0;
     double U[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < G.maxp; ++k) {
-        const int s = pslot[p * G.maxp + k];
-        if (s >= 0) {
-            U[0] += partial[3LL * s];
-            U[1] += partial[3LL * s + 1];
-            U[2] += partial[3LL * s + 2];
-        }
-    }
+#pragma unroll
+    for (int m = 0; m < 64 / ADV_GP; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) U[c] += v[m][c];
+#pragma unroll
+    for (int d = 1; d < ADV_GP; d <<= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) U[c] += __shfl_xor(U[c], d, ADV_GP);
+    if (r != 0) return;
     for (int c = 0; c < 3; ++c) {
         if (A.vel_out) A.vel_out[3 * i + c] = U[c];
         if (A.vel_sum) A.vel_sum[3 * i + c] += U[c];
@@ -537,34 +651,44 @@ void launch_fill_u32(void* p, long long n, uint32_t v, hipStream_t s)
 }
 
 void launch_prep(int storage, const Geom& G, long long n, long long off, const double* pos, const double* frc,
-                 const int* boxid, void* rec, int* count, int* pslot, int* err, hipStream_t s)
+                 const int* boxid, void* rec, int* err, hipStream_t s)
 {
     if (n <= 0) return;
     if (storage == ST_FP64)
         hipLaunchKernelGGL(k_prep<double>, dim3(nblk(n, 256)), dim3(256), 0, s, G, n, off, pos, frc, boxid,
-                           (PRec<double>*)rec, count, pslot, err);
+                           (PRec<double>*)rec, err);
     else
         hipLaunchKernelGGL(k_prep<float>, dim3(nblk(n, 256)), dim3(256), 0, s, G, n, off, pos, frc, boxid,
-                           (PRec<float>*)rec, count, pslot, err);
+                           (PRec<float>*)rec, err);
 }
 
 long long scan_blocks(long long ntiles) { return (ntiles + SCAN_B - 1) / SCAN_B; }
 
+// Steps 1b-4 over all npts points, after the records of every set are written
+// (any set may raise the rebuild flag).
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
-                 int* cursor, int* tlist, int* tlist_tmp, int* pslot, hipStream_t s)
+                 int* cursor, int* tlist, int* tlist_tmp, hipStream_t s)
 {
+    const int gp = lanes_per_point(G.maxp);
+    if (npts > 0) {
+        if (storage == ST_FP64)
+            hipLaunchKernelGGL(k_count<double>, dim3(nblk(npts * gp, 256)), dim3(256), 0, s, G, npts, 0LL, gp,
+                               (const PRec<double>*)rec, count);
+        else
+            hipLaunchKernelGGL(k_count<float>, dim3(nblk(npts * gp, 256)), dim3(256), 0, s, G, npts, 0LL, gp,
+                               (const PRec<float>*)rec, count);
+    }
     const unsigned nb = (unsigned)scan_blocks(G.ntiles);
-    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, (const int*)count, bsum);
-    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, count, (const int*)bsum, toff, cursor);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, (const int*)count, bsum,
+                       (const int*)G.rebin);
+    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, count, (const int*)bsum, toff, cursor,
+                       (const int*)G.rebin);
     if (npts <= 0) return;
-    if (storage == ST_FP64)
-        hipLaunchKernelGGL(k_fill<double>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts,
-                           (const PRec<double>*)rec, (const int*)toff, cursor, tlist_tmp);
-    else
-        hipLaunchKernelGGL(k_fill<float>, dim3(nblk(npts, 256)), dim3(256), 0, s, G, npts, (const PRec<float>*)rec,
-                           (const int*)toff, cursor, tlist_tmp);
-    hipLaunchKernelGGL(k_sort_slots, dim3(nblk(G.ntiles, 4)), dim3(256), 0, s, G, (const int*)toff,
-                       (const int*)tlist_tmp, tlist, pslot);
+    const long long max_entries = npts * G.maxp;
+    hipLaunchKernelGGL(k_fill, dim3(nblk(npts * gp, 256)), dim3(256), 0, s, G, npts, gp, (const int*)toff, cursor,
+                       tlist_tmp);
+    hipLaunchKernelGGL(k_sort_slots, dim3(nblk(max_entries, 256)), dim3(256), 0, s, G, max_entries, (const int*)toff,
+                       (const int*)tlist_tmp, tlist);
 }
 
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
@@ -581,7 +705,7 @@ void launch_box_update(int storage, const Geom& G, const void* rec, const int* t
 }
 
 
-void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, const int* pslot, const double* partial,
+void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, const double* partial,
                    hipStream_t s)
 {
     if (a.n <= 0) return;
@@ -603,7 +727,7 @@ void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, co
     A.out_scale = a.out_scale;
     A.advect = a.advect;
     A.tin = a.tin;
-    hipLaunchKernelGGL(k_advect, dim3(nblk(a.n, 256)), dim3(256), 0, s, G, A, boxes, pslot, partial);
+    hipLaunchKernelGGL(k_advect, dim3(nblk(a.n * ADV_GP, 256)), dim3(256), 0, s, G, A, boxes, partial);
 }
 
 void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,
