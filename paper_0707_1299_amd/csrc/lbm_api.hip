@@ -50,7 +50,7 @@ int max_axis_tiles(int n, int t)
 
 struct Layout {
     size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, tlist_tmp, partial, fpart, pmax, tmax, ticket, tctr,
-        err, nf, rebin, win,
+        err, nf, rebin, rebox, win,
         diag, diagout;
     size_t total;
 };
@@ -179,6 +179,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.err = take(sizeof(int) * 4);
     L.nf = take(sizeof(int) * p->nboxes);
     L.rebin = take(sizeof(int));
+    L.rebox = take(sizeof(int) * p->nboxes);
     L.win = take(sizeof(int4) * P.cap);
     L.diag = take(sizeof(double) * LBD_N * G.ntiles);
     L.diagout = take(sizeof(double) * LBD_N * p->nboxes);
@@ -250,6 +251,7 @@ struct lb_ctx {
     int* errw() const { return (int*)(ws + P.L.err); }
     int* nf() const { return (int*)(ws + P.L.nf); }
     int* rebin() const { return (int*)(ws + P.L.rebin); }
+    int* rebox() const { return (int*)(ws + P.L.rebox); }
     int4* win() const { return (int4*)(ws + P.L.win); }
     double* diag() const { return (double*)(ws + P.L.diag); }
     double* diagout() const { return (double*)(ws + P.L.diagout); }
@@ -299,6 +301,7 @@ void force_rebin(lb_ctx* c, hipStream_t s)
 {
     if (c->binned_gen == c->gen) return;
     launch_fill_u32(c->rebin(), 1, 1u, s);
+    launch_fill_u32(c->rebox(), c->p.nboxes, 1u, s);
     c->binned_gen = c->gen;
 }
 
@@ -502,6 +505,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->ws = (char*)d_workspace;
     c->P.G.nf = c->nf();
     c->P.G.rebin = c->rebin();
+    c->P.G.rebox = c->rebox();
     c->P.G.win = c->win();
     c->stream = (hipStream_t)hip_stream;
     c->cap_stream = nullptr;
@@ -562,6 +566,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     launch_fill_u32(c->errw(), 4, 0u, s);
     launch_fill_u32(c->nf(), p->nboxes, 0u, s);
     launch_fill_u32(c->rebin(), 1, 1u, s);
+    launch_fill_u32(c->rebox(), p->nboxes, 1u, s);
     launch_fill_u32(c->win(), 4 * c->P.cap, 0u, s);
     r = hip_check(c, hipMemcpyAsync(c->boxes(), c->hboxes.data(), sizeof(BoxDev) * p->nboxes, hipMemcpyHostToDevice, s),
                   "hipMemcpyAsync");

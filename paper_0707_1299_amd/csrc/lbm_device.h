@@ -95,6 +95,7 @@ struct Geom {
     int pairs;            // FP16 step: two adjacent x nodes per lane (nx even)
     int* nf;              // per box, sticky: non-finite value or FP16 overflow seen by a step
     int* rebin;           // set when a point's stencil has left its binning window (tile lists stale)
+    int* rebox;           // per box: a point of the box left its window (its windows are chosen again)
     int4* win;            // per point: window base (x, y, z) and box the tile lists were built with
     int coll;             // 1: general collision (bulk rate, ghost moments kept); 2: with thermal noise
     unsigned seed_lo, seed_hi;   // key of the noise generator

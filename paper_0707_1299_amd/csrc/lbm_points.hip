@@ -172,13 +172,17 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
     rec[p] = r;
     // skin crossing: the stencil has left the window it was binned with
     const int4 w = G.win[p];
-    if (!(in_window(r.bx, w.x, G.nx) && in_window(r.by, w.y, G.ny) && in_window(r.bz, w.z, G.nz) && w.w == box))
+    if (!(in_window(r.bx, w.x, G.nx) && in_window(r.by, w.y, G.ny) && in_window(r.bz, w.z, G.nz) && w.w == box)) {
+        atomicOr(&G.rebox[box], 1);
         atomicOr(G.rebin, 1);
+    }
 }
 
-// 1b. (only when the lists are rebuilt) choose each point's window and count the
-//    (tile, point) pairs: one group of gp lanes per point (see lanes_per_point),
-//    lane 0 storing the window, lane k counting the point in the tile of slot k.
+// 1b. (only when the lists are rebuilt) count the (tile, point) pairs: one group of
+//    gp lanes per point (see lanes_per_point), lane k counting the point in the tile
+//    of slot k.  Windows are chosen afresh (lane 0 stores them) only for the points of
+//    boxes in which a point crossed; the others keep theirs, so what a box computes
+//    never depends on crossings in the other boxes of a batch.
 template <class T>
 __global__ __launch_bounds__(256) void k_count(const Geom G, long long n, long long off, int gp,
                                                const PRec<T>* __restrict__ rec, int* __restrict__ count)
@@ -190,9 +194,11 @@ __global__ __launch_bounds__(256) void k_count(const Geom G, long long n, long l
     if (i >= n || k >= G.maxp) return;
     const long long p = off + i;
     const PRec<T> r = rec[p];
-    const int4 w = make_int4(window_base(r.bx, G.nx, r.wx), window_base(r.by, G.ny, r.wy),
-                             window_base(r.bz, G.nz, r.wz), r.box);
-    if (k == 0) G.win[p] = w;
+    const bool fresh = G.rebox[r.box] != 0;
+    const int4 w = fresh ? make_int4(window_base(r.bx, G.nx, r.wx), window_base(r.by, G.ny, r.wy),
+                                     window_base(r.bz, G.nz, r.wz), r.box)
+                         : G.win[p];
+    if (fresh && k == 0) G.win[p] = w;
     TileSet s;
     window_tiles(G, w.x, w.y, w.z, s);
     const long long t = slot_tile(G, s, r.box, k);
@@ -274,12 +280,14 @@ __global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restr
 
 // ---------------------------------------------------------------------------
 // 3. fill the per-tile point lists (slot order from atomics; fixed by step 4),
-//    one lane per (point, slot) as in step 1b.
+//    one lane per (point, slot) as in step 1b.  Also clears the per-box crossing
+//    flags (step 1b, their only reader, has finished).
 __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int gp, const int* __restrict__ toff,
                                               int* __restrict__ cursor, int* __restrict__ tlist)
 {
     if (!*G.rebin) return;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long b = gid; b < G.nboxes; b += (long long)gridDim.x * blockDim.x) G.rebox[b] = 0;
     const long long p = gid / gp;
     const int k = int(gid % gp);
     if (p >= npts) return;

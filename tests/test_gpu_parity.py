@@ -140,6 +140,42 @@ def test_colloids_advected(storage):
     assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
 
 
+@pytest.mark.parametrize("storage,tile", [("fp64", (16, 4, 4)), ("fp32", (256, 1, 1)), ("fp32", (32, 2, 4))])
+def test_colloids_cross_binning_windows(storage, tile):
+    """Colloids that leave the window of nodes they were binned with (fast sedimentation, and
+    positions rewritten between steps by more than a node) make the library rebuild its tile
+    lists; the field and the positions stay at parity through every crossing."""
+    shape = (24, 20, 28)
+    L = np.array(shape[::-1], float)
+    pos, frc = workloads.colloids(0, 12, shape=shape)
+    frc[:, 2] = -0.01          # about 0.02 nodes per step
+    model = dict(inv_a=1 / 0.117, inv_aL=0.77)
+    lat = lbm.Lattice(shape, storage, tau=0.7, zero_net_force=True, max_points=12, tile=tile)
+    p = dev(pos)
+    vel = torch.zeros_like(p)
+    lat.add_point_forces(p, dev(frc), None, lbm.LB_COLLOIDS, lbm.PointModel(vel_out=vel, **model))
+    box = oracle.Box(shape, 0.7, 1.0, zero_net_force=True)
+    box.sets = [oracle.ForceSet(pos.copy(), frc.copy(), kind="colloid", inv_a=model["inv_a"], inv_aL=model["inv_aL"])]
+    for sh in ((0.7, -1.3, 2.2), (-2.6, 0.4, -0.9), (1.1, 1.6, -1.7), (0.0, 0.0, 0.0)):
+        lat.step(30)
+        box.step(30)
+        _, u = lat.moments(rho=False)
+        lat.sync()
+        _, uo = box.moments()
+        e = rel(u.cpu().numpy()[0], uo)
+        R = p.cpu().numpy()
+        dR = np.abs(R - box.sets[0].pos)
+        dR = np.minimum(dR, L - dR).max()
+        print("cross %s %s u rel %.3e pos err %.3e" % (storage, tile, e, dR))
+        assert e <= TOL[storage]
+        assert dR <= TOL[storage] * 10
+        assert rel(vel.cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
+        # move every colloid by more than the window's margin, on both sides
+        box.sets[0].pos = np.mod(box.sets[0].pos + np.array(sh), L)
+        p.copy_(dev(np.mod(R + np.array(sh), L)))
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
 def test_equilibrium_start_and_moments(storage):
     """Shear wave started from the Eq. eqf equilibrium; density and velocity after 40 steps.
@@ -222,6 +258,35 @@ def test_batched_boxes_equal_single_runs_bitwise():
                 m = w["box"] == b
                 _, uo = run_oracle((L, L, L), taus[b], [(w["pos"][m], w["force"][m], 1, None, None)], 70, zero_net=True)
                 assert rel(ub[b], uo) <= 1e-10
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_batched_moving_boxes_equal_single_runs_bitwise(storage):
+    """Moving colloids in a batch of boxes: a box whose colloids leave their binning windows
+    (box 0, fast) rebuilds the tile lists of the whole batch, yet every box still equals its
+    one-box run bit for bit (the other boxes keep their windows)."""
+    L = 16
+    rng = np.random.default_rng(11)
+    nb, per = 3, 4
+    pos = rng.uniform(0, L, size=(nb * per, 3))
+    box = np.repeat(np.arange(nb), per).astype(np.int32)
+    frc = np.zeros_like(pos)
+    frc[:, 2] = np.where(box == 0, -0.03, -1e-4)
+    taus = [0.6, 0.8, 1.1]
+    model = dict(inv_a=1 / 0.3, inv_aL=0.77)
+    sets = [(pos, frc, lbm.LB_COLLOIDS, model, box)]
+    _, ub, outs = run_gpu((L, L, L), storage, taus, sets, 60, zero_net=True, nboxes=nb)
+    Rb = outs[0][0].cpu().numpy()
+    Ub = outs[0][1].cpu().numpy()
+    d0 = np.abs(Rb[box == 0] - pos[box == 0])
+    assert np.minimum(d0, L - d0).max() > 1.0      # box 0's colloids crossed their windows
+    for b in range(nb):
+        m = box == b
+        _, u1, o1 = run_gpu((L, L, L), storage, taus[b], [(pos[m], frc[m], lbm.LB_COLLOIDS, model, None)], 60,
+                            zero_net=True)
+        assert np.array_equal(ub[b], u1[0])
+        assert np.array_equal(Rb[m], o1[0][0].cpu().numpy())
+        assert np.array_equal(Ub[m], o1[0][1].cpu().numpy())
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "mom32"])
