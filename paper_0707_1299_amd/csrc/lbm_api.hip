@@ -143,12 +143,12 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.maxp = max_axis_tiles(p->nx, tx) * max_axis_tiles(p->ny, ty) * max_axis_tiles(p->nz, tz);
     if (G.ntiles >= (1LL << 31) - 1) { why = "too many tiles"; return LB_ERR_SIZE; }
     P.cap = p->max_points;
-    if (P.cap * G.maxp >= (1LL << 31) - 1 || P.cap >= (1LL << (31 - PK_BITS))) {
+    if (P.cap * G.maxp >= (1LL << 31) - 1 || P.cap >= (1LL << (31 - PK_SHIFT))) {
         why = "max_points too large";
         return LB_ERR_SIZE;
     }
     if (G.maxp > (1 << PK_BITS)) { why = "tile too small for the stencil"; return LB_ERR_ARG; }
-    G.bchunks = int(std::min<long long>(65535, (G.tiles_per_box + 255) / 256));
+    G.bchunks = int(std::min<long long>(256, (G.tiles_per_box + 255) / 256));
     G.tpb = 1 << ((p->variant >> 2) & 3);
     G.order = (p->variant >> 4) & 1;
     G.pairs = p->storage == LB_STORAGE_FP16 && p->nx % 2 == 0 && !((p->variant >> 5) & 1);

@@ -49,11 +49,17 @@ enum MomPlane { MP_R0 = 0, MP_AX, MP_AY, MP_AZ, MP_BXX, MP_BYY, MP_BZZ, MP_BXY, 
 
 __host__ __device__ constexpr int planes_of(int st) { return st == ST_MOM32 ? MP_N : NQ; }
 
-// Entries of the per-tile point lists: point index and the index of this tile
-// among the tiles that point's stencil touches.
+// Entries of the per-tile point lists: point index (bits 7..30), a flag marking
+// the point's home tile (bit 6: the tile holding the centre node of its binning
+// window, one per point) and the index of this tile among the tiles of the
+// point's window (bits 0..5).  Within one tile's list the order is the order of
+// the point indices.
 constexpr int PK_BITS = 6;
-__host__ __device__ constexpr int pk_point(int e) { return e >> PK_BITS; }
+constexpr int PK_HOME = 1 << PK_BITS;
+constexpr int PK_SHIFT = PK_BITS + 1;
+__host__ __device__ constexpr int pk_point(int e) { return e >> PK_SHIFT; }
 __host__ __device__ constexpr int pk_slot(int e) { return e & ((1 << PK_BITS) - 1); }
+__host__ __device__ constexpr bool pk_home(int e) { return (e & PK_HOME) != 0; }
 
 // Per-point record rebuilt before every step that needs it: base node of the
 // 4-wide stencil (floor(R) - 1, wrapped), the three sets of one-dimensional

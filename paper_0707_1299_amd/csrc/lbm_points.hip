@@ -172,9 +172,11 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
     rec[p] = r;
     // skin crossing: the stencil has left the window it was binned with
     const int4 w = G.win[p];
+    // (flags read first: after a change of the sets every point is outside its window and
+    // both flags are already raised, so no atomics queue up on one address)
     if (!(in_window(r.bx, w.x, G.nx) && in_window(r.by, w.y, G.ny) && in_window(r.bz, w.z, G.nz) && w.w == box)) {
-        atomicOr(&G.rebox[box], 1);
-        atomicOr(G.rebin, 1);
+        if (!G.rebox[box]) atomicOr(&G.rebox[box], 1);
+        if (!*G.rebin) atomicOr(G.rebin, 1);
     }
 }
 
@@ -296,8 +298,14 @@ __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int 
     window_tiles(G, w.x, w.y, w.z, s);
     const long long t = slot_tile(G, s, w.w, k);
     if (t < 0) return;
+    // home tile: the one holding the window's centre node (always inside the stencil)
+    int cx = w.x + 2, cy = w.y + 2, cz = w.z + 2;
+    if (cx >= G.nx) cx -= G.nx;
+    if (cy >= G.ny) cy -= G.ny;
+    if (cz >= G.nz) cz -= G.nz;
+    const bool home = t == tile_id(G, w.w, cz / G.tz, cy / G.ty, cx / G.tx);
     const int slot = toff[t] + atomicAdd(&cursor[t], 1);
-    tlist[slot] = int(p << PK_BITS) | k;
+    tlist[slot] = int(p << PK_SHIFT) | (home ? PK_HOME : 0) | k;
 }
 
 // 4. sort every tile's list by point index (so sums run in a fixed order).  One
@@ -326,9 +334,10 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_
 // 5. per-box work before a step: the counter-force density -sum F / N and, for
 //    FP16 storage, the exponent of the data written by the coming step, chosen
 //    from the largest bracket of the last one.  The force sum visits each point
-//    once, in its home tile (the tile of node floor(R)), over the box's own
-//    tiles in a fixed chunking, so the result does not depend on how many
-//    boxes share the launch or on the order the bins were filled.
+//    once, at its home entry (flagged when the lists are built), striding over
+//    the box's own span of the lists in a fixed chunking, so the result does not
+//    depend on the other boxes that share the launch or on the order in which
+//    the bins were filled.
 template <class T>
 __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>* __restrict__ rec,
                                                     const int* __restrict__ toff, const int* __restrict__ tlist,
@@ -336,28 +345,24 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
                                                     float* __restrict__ pmax, unsigned* __restrict__ ticket,
                                                     BoxDev* __restrict__ boxes, int zero_net, int fp16_exp)
 {
-    // block (b, c) covers tiles [256 c, 256 c + 256) of box b, one tile per thread
+    // block (b, c) covers tiles 256 c + thread + 256 C j of box b and the list entries
+    // at the same offsets in the box's span (C at most 256: one ticket per block)
     const int b = blockIdx.x, c = blockIdx.y, C = gridDim.y;
     const long long t = (long long)c * blockDim.x + threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
     float m = 0.0f;
-    if (t < G.tiles_per_box) {
-        const long long tt = (long long)b * G.tiles_per_box + t;
-        if (fp16_exp) m = tmax[tt];
-        if (zero_net && toff) {
-            for (int k = toff[tt]; k < toff[tt + 1]; ++k) {
-                const PRec<T>& r = rec[pk_point(tlist[k])];
-                int hx = r.bx + 1, hy = r.by + 1, hz = r.bz + 1;
-                if (hx == G.nx) hx = 0;
-                if (hy == G.ny) hy = 0;
-                if (hz == G.nz) hz = 0;
-                const long long home =
-                    (((long long)r.box * G.ntz + hz / G.tz) * G.nty + hy / G.ty) * G.ntx + hx / G.tx;
-                if (home == tt) {
-                    s[0] += double(r.f[0]);
-                    s[1] += double(r.f[1]);
-                    s[2] += double(r.f[2]);
-                }
+    if (fp16_exp)
+        for (long long u = t; u < G.tiles_per_box; u += (long long)C * blockDim.x)
+            m = fmaxf(m, tmax[(long long)b * G.tiles_per_box + u]);
+    if (zero_net && toff) {
+        const long long e0 = toff[(long long)b * G.tiles_per_box], e1 = toff[(long long)(b + 1) * G.tiles_per_box];
+        for (long long e = e0 + t; e < e1; e += (long long)C * blockDim.x) {
+            const int v = tlist[e];
+            if (pk_home(v)) {
+                const PRec<T>& r = rec[pk_point(v)];
+                s[0] += double(r.f[0]);
+                s[1] += double(r.f[1]);
+                s[2] += double(r.f[2]);
             }
         }
     }
