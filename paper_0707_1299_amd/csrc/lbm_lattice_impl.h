@@ -152,6 +152,12 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         }
         for (int k = k0; k < k1; ++k) {
             const PRec<T>& r = rec[pk_point(tlist[k])];
+            // rows the point's stencil misses take nothing from it: skip them (a scalar branch
+            // when y and z are wave-uniform; otherwise waves whose lanes all miss skip it)
+            int dy = y - r.by, dz = z - r.bz;
+            if (dy < 0) dy += G.ny;
+            if (dz < 0) dz += G.nz;
+            if (dy > 3 || dz > 3) continue;
             const T w = stencil_w<T>(xh, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
                         stencil_w<T>(z, r.bz, G.nz, r.wz);
             gx += r.f[0] * w;
