@@ -474,19 +474,10 @@ __device__ float mlp_eval(const float* __restrict__ W, const float (&xin)[4])
     return y;
 }
 
-__global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
-                                                const double* __restrict__ partial)
+// The group's sum of point p's partials (every lane of the group returns the same bits).
+__device__ __forceinline__ void group_sum(const Geom& G, const double* __restrict__ partial, long long p, int r,
+                                          double (&U)[3])
 {
-    __shared__ float W[LBML_NPARAM_DEV];
-    if (A.mlp) {
-        for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) W[k] = bf16_to_f32(A.mlp[k]);
-        __syncthreads();
-    }
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long i = gid / ADV_GP;
-    const int r = int(gid % ADV_GP);
-    if (i >= A.n) return;   // whole groups: a group is 8 aligned lanes of one wave
-    const long long p = A.off + i;
     // the point's partials, one per tile of its window (nt <= maxp <= 64 slots)
     const int4 win = G.win[p];
     const int nt = axis_count(win.x, G.nx, G.tx) * axis_count(win.y, G.ny, G.ty) * axis_count(win.z, G.nz, G.tz);
@@ -496,7 +487,7 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
     for (int m = 0; m < 64 / ADV_GP; ++m)
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[m][c] = r + m * ADV_GP < nt ? pp[(r + m * ADV_GP) * 3 + c] : 0.0;
-    double U[3] = {0.0, 0.0, 0.0};
+    U[0] = U[1] = U[2] = 0.0;
 #pragma unroll
     for (int m = 0; m < 64 / ADV_GP; ++m)
 #pragma unroll
@@ -505,7 +496,14 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
     for (int d = 1; d < ADV_GP; d <<= 1)
 #pragma unroll
         for (int c = 0; c < 3; ++c) U[c] += __shfl_xor(U[c], d, ADV_GP);
-    if (r != 0) return;
+}
+
+// Outputs and the move of point i (set-local; p = A.off + i) with interpolated velocity U;
+// W: the MLP weights in LDS (used only with A.mlp).
+__device__ __forceinline__ void finish_point(const Geom& G, const AdvectArgs& A, const BoxDev* __restrict__ boxes,
+                                             long long i, long long p, const double (&U)[3],
+                                             const float* __restrict__ W)
+{
     for (int c = 0; c < 3; ++c) {
         if (A.vel_out) A.vel_out[3 * i + c] = U[c];
         if (A.vel_sum) A.vel_sum[3 * i + c] += U[c];
@@ -540,6 +538,53 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
     }
     for (int a = 0; a < 3; ++a)
         A.pos[3 * i + a] = wrap_pos(R[a] + (U[a] + zeta[a]) + A.frc[3 * i + a] * mob, L[a]);
+}
+
+// Without the MLP: one group per point, lane 0 of the group finishes it.
+__global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
+                                                const double* __restrict__ partial)
+{
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = gid / ADV_GP;
+    const int r = int(gid % ADV_GP);
+    if (i >= A.n) return;   // whole groups: a group is 8 aligned lanes of one wave
+    double U[3];
+    group_sum(G, partial, A.off + i, r, U);
+    if (r == 0) finish_point(G, A, boxes, i, A.off + i, U, nullptr);
+}
+
+// With the MLP (a few thousand FLOP per point, which wants every lane busy): the group
+// sums leave U in the point's first partial slot (rewritten by the next step), then one
+// lane per point finishes with the weights staged in LDS.
+__global__ __launch_bounds__(256) void k_advect_sum(const Geom G, long long n, long long off,
+                                                    double* __restrict__ partial)
+{
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = gid / ADV_GP;
+    const int r = int(gid % ADV_GP);
+    if (i >= n) return;
+    double U[3];
+    group_sum(G, partial, off + i, r, U);
+    if (r == 0) {
+        double* pp = partial + (off + i) * G.maxp * 3;
+        pp[0] = U[0];
+        pp[1] = U[1];
+        pp[2] = U[2];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_advect_mlp(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
+                                                    const double* __restrict__ partial)
+{
+    __shared__ float W[LBML_NPARAM_DEV];
+    for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) W[k] = bf16_to_f32(A.mlp[k]);
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const long long p = A.off + i;
+    const double* pp = partial + p * G.maxp * 3;
+    const double U[3] = {pp[0], pp[1], pp[2]};
+    finish_point(G, A, boxes, i, p, U, W);
 }
 
 // ---------------------------------------------------------------------------
@@ -718,7 +763,7 @@ void launch_box_update(int storage, const Geom& G, const void* rec, const int* t
 }
 
 
-void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, const double* partial,
+void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial,
                    hipStream_t s)
 {
     if (a.n <= 0) return;
@@ -740,7 +785,12 @@ void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, co
     A.out_scale = a.out_scale;
     A.advect = a.advect;
     A.tin = a.tin;
-    hipLaunchKernelGGL(k_advect, dim3(nblk(a.n * ADV_GP, 256)), dim3(256), 0, s, G, A, boxes, partial);
+    if (A.mlp) {
+        hipLaunchKernelGGL(k_advect_sum, dim3(nblk(a.n * ADV_GP, 256)), dim3(256), 0, s, G, a.n, a.off, partial);
+        hipLaunchKernelGGL(k_advect_mlp, dim3(nblk(a.n, 256)), dim3(256), 0, s, G, A, boxes, (const double*)partial);
+    } else {
+        hipLaunchKernelGGL(k_advect, dim3(nblk(a.n * ADV_GP, 256)), dim3(256), 0, s, G, A, boxes, (const double*)partial);
+    }
 }
 
 void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,
