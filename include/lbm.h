@@ -89,8 +89,7 @@ typedef struct lb_params {
     int32_t zero_net_force; /* 1: add the uniform density -sum F / N per box */
     double rho0;            /* reference density (> 0); 0 means 1 */
     const double* tau;      /* HOST array [nboxes]: paper's tau (> 0) per box */
-    int64_t max_points;     /* capacity: point forces over all sets at once; below 2^24, and
-                               max_points * (tiles of a 5-node window) below 2^31
+    int64_t max_points;     /* capacity: point forces over all sets at once; below 2^24
                                (LB_ERR_SIZE otherwise) */
     int32_t tile_x;         /* tile shape (nodes); 0 = default. tile_x*tile_y*tile_z = 256 */
     int32_t tile_y;

@@ -94,7 +94,7 @@ struct Geom {
     int nx, ny, nz, nboxes;
     int tx, ty, tz;       // tile extent per axis (tx * ty * tz == BLOCK)
     int ntx, nty, ntz;    // tiles per axis
-    int maxp;             // max tiles touched by one point's stencil
+    int maxp;             // most tiles met by one point's binning window (5 nodes per axis)
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
     int order;            // 0: blocks renumbered into contiguous runs per XCD; 1: launch order

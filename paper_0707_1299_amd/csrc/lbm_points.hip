@@ -1,5 +1,6 @@
 // Point-force kernels: per-point stencil records, deterministic binning of
-// points to the lattice tiles their stencils touch, per-box force sums and
+// points to the lattice tiles of a window around their stencils (rebuilt only
+// when a stencil leaves its window), per-box force sums and
 // FP16 exponents, the colloid update, interpolation at arbitrary points and
 // the reduction of the diagnostics.
 //

@@ -73,6 +73,16 @@ def test_bad_params_rejected(kw):
     assert e.value.status in (lbm.LB_ERR_ARG, lbm.LB_ERR_SIZE)
 
 
+def test_point_capacity_limits():
+    """List entries pack the point index in 24 bits: 2^24 - 1 points are accepted, 2^24 are
+    refused at set-up (with at most 64 tiles per point the entry count stays below 2^31)."""
+    ok = lbm.lb_workspace_bytes(lbm.make_params((16, 16, 256), "fp32", max_points=(1 << 24) - 1, tile=(32, 4, 2)))
+    assert ok > 0
+    with pytest.raises(lbm.LBError) as e:
+        lbm.lb_workspace_bytes(lbm.make_params((16, 16, 256), "fp32", max_points=1 << 24, tile=(32, 4, 2)))
+    assert e.value.status == lbm.LB_ERR_SIZE
+
+
 def test_status_strings():
     for code in (lbm.LB_OK, lbm.LB_ERR_ARG, lbm.LB_ERR_SIZE, lbm.LB_ERR_HIP, lbm.LB_ERR_NONFINITE,
                  lbm.LB_ERR_CAPACITY, lbm.LB_ERR_STATE):
