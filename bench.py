@@ -378,7 +378,7 @@ def main():
     copy_gbs, copy_same_gbs = stream_copy_gbs(1 << 30), stream_copy_gbs(same_bytes)
     shape, storage, tau, kind, n, pos, frc, fkind, model = inp
     traffic = traffic_from_profile(a.workload, storage, r["nodes"])
-    tile, variant = tuned(shape, storage, 1, a.workload)
+    tile, variant = tuned(shape, storage, n if kind == "boxes" else 1, a.workload)
     out = {
         "metric": "MLUPS and % HBM roofline; colloid updates/s vs plain FP32 at stated error",
         "value": round(r["mlups"], 1),
