@@ -357,14 +357,29 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
             m = fmaxf(m, tmax[(long long)b * G.tiles_per_box + u]);
     if (zero_net && toff) {
         const long long e0 = toff[(long long)b * G.tiles_per_box], e1 = toff[(long long)(b + 1) * G.tiles_per_box];
-        for (long long e = e0 + t; e < e1; e += (long long)C * blockDim.x) {
-            const int v = tlist[e];
-            if (pk_home(v)) {
-                const PRec<T>& r = rec[pk_point(v)];
-                s[0] += double(r.f[0]);
-                s[1] += double(r.f[1]);
-                s[2] += double(r.f[2]);
+        const long long S = (long long)C * blockDim.x;
+        // the thread's entries e0 + t + S j in increasing j, eight at a time: all list loads,
+        // then the forces of the home entries, then the sums in that same order
+        for (long long e = e0 + t; e < e1; e += 8 * S) {
+            int v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = e + j * S < e1 ? tlist[e + j * S] : 0;   // 0: not a home entry
+            T f[8][3];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool h = pk_home(v[j]);
+                const PRec<T>& r = rec[h ? pk_point(v[j]) : 0];
+                f[j][0] = h ? r.f[0] : T(0);
+                f[j][1] = h ? r.f[1] : T(0);
+                f[j][2] = h ? r.f[2] : T(0);
             }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (pk_home(v[j])) {
+                    s[0] += double(f[j][0]);
+                    s[1] += double(f[j][1]);
+                    s[2] += double(f[j][2]);
+                }
         }
     }
     __shared__ double red[4][3];
