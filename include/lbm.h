@@ -189,7 +189,11 @@ int lb_set_equilibrium(lb_ctx* ctx, const double* d_rho, const double* d_u);
  * LB_FORCES_NEXT_STEP and LB_COLLOIDS arrays are read at every step that
  * applies them; LB_FORCES_STATIC arrays are read once, before the first step
  * after registration (re-register to change them).  All must stay valid until
- * the work that reads them has run (stream order).  Forces spread per
+ * the work that reads them has run (stream order).  Positions and box ids of the
+ * sets read every step may be rewritten between steps by any amount: each point
+ * is binned to the tiles of a 5-node window per axis around its stencil, and
+ * the tile lists are rebuilt in the step at which a stencil has left its window
+ * (or its box changed), choosing new windows for the points of that box only.  Forces spread per
  * Sec. III; multipoles are passed as their point forces (see
  * lb_expand_multipoles).  With FP16 storage the scale exponent follows the
  * data with one step of delay: a jump of more than 4x in the largest
