@@ -279,7 +279,7 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False, choice=None):
 def tune_workload(name, steps=40, refine=5):
     """Every candidate (tile, variant) of the tuner on this workload as it is timed (its points,
     markers, collision options), then the `refine` fastest again over 5x the steps (short runs
-    differ by a few per cent from run to run); the fastest whole step of the second round is
+    differ by a few per cent from run to run); the fastest whole step of the second pass is
     cached under the workload's name."""
     from paper_0707_1299_amd import tune
     shape, storage, tau, kind, n = WORKLOADS[name]
