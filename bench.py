@@ -358,6 +358,8 @@ def main():
     ap.add_argument("--all", action="store_true", help="also time the other workloads (reported under 'workloads')")
     ap.add_argument("--tune", action="store_true",
                     help="sweep tile x access variant on this workload and cache the fastest step under its name")
+    ap.add_argument("--mlp", action="store_true",
+                    help="colloid workloads: advance with the learned mobility correction (the MLP)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 10 device copies of 512 MiB (reference for the HBM byte counters)")
     a = ap.parse_args()
@@ -385,7 +387,10 @@ def main():
     import torch
     from paper_0707_1299_amd import lbm  # noqa: F401  (fails loudly if the library is missing)
 
-    r, inp = run_workload(a.workload, a.steps, a.warmup, a.timing_steps)
+    if a.mlp and WORKLOADS[a.workload][3] not in ("colloids", "slab"):
+        print("--mlp applies to the colloid workloads only", file=sys.stderr)
+        sys.exit(2)
+    r, inp = run_workload(a.workload, a.steps, a.warmup, a.timing_steps, mlp=a.mlp)
     same_bytes = BYTES_PER_NODE[inp[1]] * r["nodes"] // 2          # one population copy of the workload
     copy_gbs, copy_same_gbs = stream_copy_gbs(1 << 30), stream_copy_gbs(same_bytes)
     shape, storage, tau, kind, n, pos, frc, fkind, model = inp
@@ -404,7 +409,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-storage/f32", "mom32": "f32"}[storage],
         "data": "synthetic",
-        "config": {"workload": describe(a.workload, r), "nodes": r["nodes"], "points": r["points"],
+        "config": {"workload": describe(a.workload, r) + (" + MLP mobility correction" if a.mlp else ""),
+                   "nodes": r["nodes"], "points": r["points"],
                    "seed": 20261200 + {"singularities": 2, "colloids": 3, "slab": 3, "boxes": 4, "droplets": 5, "chains": 6}[kind],
                    "tile": list(tile or ()), "variant": variant},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -419,7 +425,8 @@ def main():
     if "colloid_updates_per_s" in r:
         out["colloid_updates_per_s"] = round(r["colloid_updates_per_s"], 1)
 
-    if not a.no_cpu and kind in ("singularities", "colloids", "slab") and a.workload not in OPTS:
+    # (the CPU leg times the oracle's plain colloid update: none with --mlp)
+    if not a.no_cpu and not a.mlp and kind in ("singularities", "colloids", "slab") and a.workload not in OPTS:
         box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model)
         out["cpu_baseline"] = cb
         # same number of steps on a fresh GPU lattice: error of this storage against the oracle

@@ -19,6 +19,13 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
+def test_mlp_only_for_colloid_workloads():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mlp", "--workload", "singularities128"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2
+    assert "colloid" in r.stderr
+
+
 def _record(tmp_path, monkeypatch, **over):
     """A traffic record for the default workload in a scratch profiles/ folder."""
     shape, storage = bench.WORKLOADS["singularities128"][0], bench.WORKLOADS["singularities128"][1]
