@@ -4,9 +4,19 @@ FP64 CPU oracle timed beside it.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME] [--no-cpu]
 
-Default workload: 128^3 periodic box, FP32 deviation storage, tau = 1/2,
-64 seeded singularities (Stokeslets, stresslets, rotlets; strengths uniform
-in [-1e-5, 1e-5]) expanded to their point forces, static, 5000 steps.
+Default (--workload headline): the 512^3 periodic lattice with 10^5
+sedimenting point colloids (F = -1e-6 z, a = 0.684, volume fraction ~1e-3,
+tau = 1/2, counter-force on), spread + step + interpolate + advect every step,
+in two forms:
+  * plain: FP32 deviation storage, the constant 1/a_L fitted for tau = 1/2
+    (`value`, the fused kernel's `roofline`);
+  * chosen: FP16-scaled storage and the trained mobility network
+    (paper_0707_1299_amd/mobility_net.json) in the colloid update
+    (`chosen_form`, with its own roofline);
+with the colloid updates per second of both, the mobility error of both
+against single-particle full-lattice runs at tau = 1/2, the error of both
+against the FP64 oracle after a few steps, and the oracle's own rate on the
+same 512^3 workload (`cpu_baseline`).  Other workloads: --workload NAME.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -105,9 +115,23 @@ def make_inputs(kind, shape, n):
         pos, frc = workloads.colloids(shape[2], n, shape=shape)
         return pos, frc, "colloid", dict(inv_a=1 / 0.684, inv_aL=0.77)
     pos, frc = workloads.colloids(L, n)
-    # a = 0.117 (Table 1) at 256^3; a = 0.684 (volume fraction ~1e-3 with 10^5 colloids) at 512^3
-    a = 0.684 if L >= 512 else 0.117
-    return pos, frc, "colloid", dict(inv_a=1 / a, inv_aL=0.77)
+    # a = 0.117 (Table 1) at 256^3 with 1/a_L = 0.77; a = 0.684 (volume fraction ~1e-3 with 10^5
+    # colloids) at 512^3 with the plain 1/a_L fitted for the run's tau
+    if L >= 512:
+        return pos, frc, "colloid", dict(inv_a=1 / 0.684, inv_aL=None)
+    return pos, frc, "colloid", dict(inv_a=1 / 0.117, inv_aL=0.77)
+
+
+def point_model(model, tau):
+    """The colloid model of a workload: model["mlp"] True uses the trained network
+    (mobility_net.json) in the update; model["inv_aL"] None the plain constant fitted for tau."""
+    from paper_0707_1299_amd import lbm, mobility
+    if model.get("mlp") or model.get("inv_aL") is None:
+        tr = mobility.load(mobility.DEFAULT_NET)
+        if model.get("mlp"):
+            return tr.model(model["inv_a"])
+        return tr.plain_model(model["inv_a"], tau)
+    return lbm.PointModel(inv_a=model["inv_a"], inv_aL=model["inv_aL"])
 
 
 def tuned(shape, storage, nboxes=1, tag=None):
@@ -149,24 +173,16 @@ def build_lattice(shape, storage, tau, kind, pos, frc, model, opts=None, name=No
     p = torch.tensor(pos, dtype=torch.float64, device="cuda")
     f = torch.tensor(frc, dtype=torch.float64, device="cuda")
     if kind == "colloid":
-        pm = lbm.PointModel(**{k: v for k, v in model.items() if k != "mlp_seed"})
-        if model.get("mlp_seed") is not None:
-            # network of the learned correction (random weights: same cost as trained ones)
-            from paper_0707_1299_amd import mobility
-            master = torch.tensor(mobility.init_master(model["mlp_seed"]), device="cuda")
-            w16 = torch.zeros(lbm.LBML_NPARAM, dtype=torch.int16, device="cuda")
-            lbm.lbml_round_bf16(master, w16)
-            pm.mlp, pm.in_shift, pm.in_scale, pm.out_scale = w16, mobility.IN_SHIFT, mobility.IN_SCALE, 1e-3
-        lat.add_point_forces(p, f, None, lbm.LB_COLLOIDS, pm)
+        lat.add_point_forces(p, f, None, lbm.LB_COLLOIDS, point_model(model, tau))
     else:
         lat.add_point_forces(p, f, None, lbm.LB_FORCES_STATIC)
     return lat, p
 
 
-def traffic_from_profile(name, storage, N):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+def traffic_from_profile(name, storage, N, record=None):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (profiles/traffic_<record or
+    name>.json), if it was taken on the current kernel source and launch choice; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % (record or name))
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -179,19 +195,41 @@ def traffic_from_profile(name, storage, N):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(kind, shape, storage, tau, pos, frc, model, budget_s=12.0):
+def oracle_model(model, tau):
+    """(inv_a, inv_aL, inv_aL_fn) of the oracle's colloid update for a workload's model: the same
+    constant, or the same bf16 network evaluated in FP64."""
+    if not model:
+        return 0.0, 0.0, None
+    pm = point_model(model, tau)
+    if not model.get("mlp"):
+        return pm.inv_a, pm.inv_aL, None
+    import numpy as np
+    from oracle import mlp as omlp
+    from paper_0707_1299_amd import mobility
+    tr = mobility.load(mobility.DEFAULT_NET)
+    theta = mobility.weights_f64(tr)
+
+    def inv_aL_fn(p, t):
+        o = p - np.floor(p)
+        y, _ = omlp.forward(theta, mobility.features(o, np.full(len(p), t)), round_bf16=False)
+        return tr.mu_plain + tr.out_scale * y
+
+    return pm.inv_a, pm.inv_aL, inv_aL_fn
+
+
+def cpu_baseline(kind, shape, storage, tau, pos, frc, model, budget_s=12.0, max_steps=200):
     """The FP64 oracle, as it is, on a bounded number of steps of the same workload."""
     import numpy as np
     import oracle
     box = oracle.Box(shape, tau, 1.0, zero_net_force=(kind == "colloid"))
-    fs = oracle.ForceSet(np.array(pos), np.array(frc), kind=kind,
-                         inv_a=(model or {}).get("inv_a", 0.0), inv_aL=(model or {}).get("inv_aL", 0.0))
+    inv_a, inv_aL, fn = oracle_model(model, tau) if kind == "colloid" else (0.0, 0.0, None)
+    fs = oracle.ForceSet(np.array(pos), np.array(frc), kind=kind, inv_a=inv_a, inv_aL=inv_aL, inv_aL_fn=fn)
     box.sets = [fs]
     t0 = time.perf_counter()
     box.step(1)
     t1 = time.perf_counter()
     per = t1 - t0
-    steps = int(max(1, min(200, budget_s / max(per, 1e-6))))
+    steps = int(max(1, min(max_steps, budget_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     box.step(steps)
     dt = time.perf_counter() - t0
@@ -244,7 +282,7 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False, choice=None):
     N = shape[0] * shape[1] * shape[2] * nb
     pos, frc, fkind, model = make_inputs(kind, shape, n)
     if mlp and model is not None:
-        model = dict(model, mlp_seed=0)
+        model = dict(model, mlp=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(name), name, choice)
@@ -347,14 +385,150 @@ def describe(name, r):
     return d
 
 
+def roofline(r, storage, traffic, copy_gbs=None, copy_same_gbs=None):
+    """The fused step kernel's HBM roofline entry for one timed workload."""
+    d = {"bound": "hbm", "achieved": round(r["achieved_GBs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+         "frac": round(r["frac"], 4), "traffic": traffic,
+         "kernel": "k_lattice step (fused spread/pull/collide/store/interpolate)",
+         "bytes_per_node": BYTES_PER_NODE[storage], "kernel_ms": round(r["kernel_ms"], 5),
+         "launches_timed": r["launches_timed"]}
+    if copy_gbs:
+        d.update(copy_1GiB_GBs=round(copy_gbs, 1), frac_of_copy=round(r["achieved_GBs"] / copy_gbs, 4))
+    if copy_same_gbs:
+        d.update(copy_same_bytes_GBs=round(copy_same_gbs, 1),
+                 frac_of_copy_same_bytes=round(r["achieved_GBs"] / copy_same_gbs, 4))
+    return d
+
+
+def mobility_error(n=128, tau=0.5, L=32):
+    """Self-mobility error of the plain constant (fitted for tau) and of constant + network, against
+    fresh single-particle full-lattice runs (one fixed colloid per 32^3 box, 2000 steps, the last 200
+    averaged) at seeded offsets the network was not trained on."""
+    import numpy as np
+    from paper_0707_1299_amd import mobility, workloads
+    tr = mobility.load(mobility.DEFAULT_NET)
+    off = workloads.rng(8).uniform(0, 1, size=(n, 3))
+    taus = np.full(n, tau)
+    mu = mobility.self_part(mobility.single_particle_labels(off, taus, L=L, steps=2000, average=200), L)
+    ev = mobility.evaluate(tr, off, taus, mu)
+    return {"reference": "%d single-particle %d^3 runs at tau=%g (fixed colloid, 2000 steps, U averaged over the "
+                         "last 200), seeded offsets not in the training set; mu = 6 pi eta U.F/|F|^2 + 2.84/L"
+                         % (n, L, tau),
+            "mu_mean": round(ev["mu_mean"], 5),
+            "plain": {"rms": ev["rms_plain_tau"], "max": ev["max_plain_tau"], "inv_aL": float(tr.plain_tau(tau))},
+            "mlp": {"rms": ev["rms_mlp"], "max": ev["max_mlp"]},
+            "gain_rms": round(ev["rms_plain_tau"] / ev["rms_mlp"], 2)}
+
+
+def oracle_error(name, csteps, box, model_over=None):
+    """A fresh GPU run of the workload for csteps steps against the oracle box that ran them:
+    velocity field, interpolated velocity and positions (relative to the oracle's displacement)."""
+    import numpy as np
+    import torch
+    shape, storage, tau, kind, n = WORKLOADS[name]
+    pos, frc, fkind, model = make_inputs(kind, shape, n)
+    if model_over:
+        model = dict(model, **model_over)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(name), name)
+        lat.step(csteps)
+        _, u = lat.moments(rho=False)
+        lat.sync()
+        ug = u[0].cpu().numpy()
+        Rg = dpos.cpu().numpy()
+        lat.close()
+    del u
+    torch.cuda.empty_cache()
+    _, uo = box.moments()
+    out = {"steps": csteps, "velocity_rel_linf": float(np.abs(ug - uo).max() / np.abs(uo).max())}
+    if fkind == "colloid":
+        ext = np.array(shape[::-1], dtype=np.float64)
+        d = np.abs(Rg - box.sets[0].pos)
+        d = np.minimum(d, ext - d)
+        m = np.abs(box.sets[0].pos - pos)
+        m = np.minimum(m, ext - m)
+        out["position_err_over_displacement"] = float(d.max() / m.max())
+    return out
+
+
+def headline(a):
+    """The 512^3 workload with 10^5 colloids: plain FP32 (value) and FP16 + trained network."""
+    import torch
+    plain, chosen = "colloids512_fp32", "colloids512_fp16"
+    r32, inp32 = run_workload(plain, a.steps, a.warmup, a.timing_steps)
+    print("plain fp32 timed", file=sys.stderr, flush=True)
+    r16, inp16 = run_workload(chosen, a.steps, a.warmup, a.timing_steps, mlp=True)
+    print("fp16 + network timed", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    copy_gbs = stream_copy_gbs(1 << 30)
+    copy_same = stream_copy_gbs(BYTES_PER_NODE["fp32"] * r32["nodes"] // 2)
+    shape = WORKLOADS[plain][0]
+    t32, v32 = tuned(shape, "fp32", 1, plain)
+    t16, v16 = tuned(shape, "fp16", 1, chosen)
+    out = {
+        "metric": "MLUPS and % HBM roofline; colloid updates/s vs plain FP32 at stated error",
+        "value": round(r32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 periodic D3Q19 forced MRT, tau=1/2, 10^5 sedimenting point colloids (seeded "
+                               "uniform positions, F=-1e-6 z, a=0.684, volume fraction ~1e-3), counter-force on; "
+                               "spread + fused step + interpolate + advect every step. value: plain form (FP32 "
+                               "deviation storage, constant 1/a_L fitted for tau=1/2)",
+                   "nodes": r32["nodes"], "colloids": r32["points"], "seed": 20261203,
+                   "tile": list(t32 or ()), "variant": v32},
+        "roofline": roofline(r32, "fp32", traffic_from_profile(plain, "fp32", r32["nodes"]), copy_gbs, copy_same),
+        "colloid_updates_per_s": round(r32["colloid_updates_per_s"], 1),
+        "chosen_form": {
+            "form": "FP16-scaled deviation storage (FP32 arithmetic) + trained 4-64-64-1 bf16 mobility network "
+                    "in the colloid update",
+            "mlups": round(r16["mlups"], 1), "ms_per_step": round(r16["ms_per_step"], 5),
+            "colloid_updates_per_s": round(r16["colloid_updates_per_s"], 1),
+            "speedup_vs_plain": round(r16["mlups"] / r32["mlups"], 4),
+            "tile": list(t16 or ()), "variant": v16,
+            "roofline": roofline(r16, "fp16", traffic_from_profile(chosen, "fp16", r16["nodes"], chosen + "_mlp"))},
+    }
+    out["mobility_error"] = mobility_error()
+    print("mobility error leg done", file=sys.stderr, flush=True)
+    if not a.no_cpu:
+        shape, storage, tau, kind, n, pos, frc, fkind, model = inp32
+        box, csteps, cb = cpu_baseline(fkind, shape, storage, tau, pos, frc, model, budget_s=10.0, max_steps=8)
+        cb["sample"] += " (the 512^3 workload with 10^5 colloids, plain form)"
+        out["cpu_baseline"] = cb
+        errs = {"plain_fp32": oracle_error(plain, csteps, box)}
+        del box
+        print("oracle plain leg done", file=sys.stderr, flush=True)
+        shape, storage, tau, kind, n, pos, frc, fkind, model = inp16
+        import oracle
+        inv_a, inv_aL, fn = oracle_model(dict(model, mlp=True), tau)
+        box = oracle.Box(shape, tau, 1.0, zero_net_force=True)
+        box.sets = [oracle.ForceSet(pos.copy(), frc.copy(), kind="colloid", inv_a=inv_a, inv_aL=inv_aL,
+                                    inv_aL_fn=fn)]
+        box.step(csteps)
+        errs["chosen_fp16_mlp"] = oracle_error(chosen, csteps, box, dict(mlp=True))
+        del box
+        out["error_vs_oracle"] = errs
+        out["oracle_cpu"] = cpu_model()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="singularities128", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 200 for the headline, else 5000)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 20 for the headline, else 200)")
+    ap.add_argument("--workload", default="headline", choices=["headline"] + sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--timing-steps", type=int, default=500)
+    ap.add_argument("--timing-steps", type=int, default=None,
+                    help="eager steps timed per kernel launch (default 50 for the headline, else 500)")
     ap.add_argument("--all", action="store_true", help="also time the other workloads (reported under 'workloads')")
     ap.add_argument("--tune", action="store_true",
                     help="sweep tile x access variant on this workload and cache the fastest step under its name")
@@ -387,6 +561,13 @@ def main():
     import torch
     from paper_0707_1299_amd import lbm  # noqa: F401  (fails loudly if the library is missing)
 
+    hl = a.workload == "headline"
+    a.steps = a.steps if a.steps is not None else (200 if hl else 5000)
+    a.warmup = a.warmup if a.warmup is not None else (20 if hl else 200)
+    a.timing_steps = a.timing_steps if a.timing_steps is not None else (50 if hl else 500)
+    if hl:
+        headline(a)
+        return
     if a.mlp and WORKLOADS[a.workload][3] not in ("colloids", "slab"):
         print("--mlp applies to the colloid workloads only", file=sys.stderr)
         sys.exit(2)

@@ -53,6 +53,7 @@ extern "C" {
 #define LB_ERR_NONFINITE (-4) /* non-finite value or FP16 overflow detected */
 #define LB_ERR_CAPACITY (-5)  /* more point forces than max_points */
 #define LB_ERR_STATE (-6)     /* call not valid in the current state */
+#define LB_ERR_NEGATIVE_DENSITY (-7) /* a node's density rho0 + drho is <= 0 (lb_diagnostics) */
 
 /* population storage */
 #define LB_STORAGE_FP64 0 /* FP64 deviations, FP64 arithmetic */
@@ -77,7 +78,7 @@ extern "C" {
 #define LB_COLLOIDS 2         /* applied every step; positions advanced in place */
 
 #define LB_MAX_SETS 16
-#define LB_NDIAG 12 /* values per box returned by lb_diagnostics */
+#define LB_NDIAG 13 /* values per box returned by lb_diagnostics */
 
 /* MLP of the learned mobility correction: 4 -> 64 tanh -> 64 tanh -> 1 */
 #define LBML_NPARAM 4545
@@ -257,7 +258,9 @@ int lb_clear_forces(lb_ctx* ctx);
  * current positions, collide every node with them (Eq. fiexp), interpolate the
  * physical velocity u at the points with the same kernel, propagate (the split
  * after Eq. halftransform), then advance colloids by the Sec. IV update
- * (explicit Euler).  Repeated chunks run as a captured HIP graph.
+ * (explicit Euler).  Repeated chunks of 2, 4, ..., 32 steps run as captured
+ * HIP graphs (captured on first use per chunk length, parity and set of
+ * registered forces).
  */
 int lb_step(lb_ctx* ctx, int32_t nsteps);
 
@@ -278,13 +281,38 @@ int lb_interp_velocity(lb_ctx* ctx, int64_t n, const double* d_pos, const int32_
  * FP64 diagnostics per box, written to HOST h_out[nboxes][LB_NDIAG]:
  *   0 sum drho, 1-3 sum jbar (auxiliary momentum), 4-6 sum g,
  *   7-9 sum x cross g (node coordinates in the box), 10 max |u|,
- *   11 count of non-finite nodes.  Waits for the stream.  Returns
- *   LB_ERR_NONFINITE if any box holds a non-finite value.
+ *   11 count of non-finite nodes, 12 count of nodes whose density
+ *   rho0 + drho is not positive (finite nodes only).  Waits for the stream.
+ *   Returns LB_ERR_NONFINITE if any box holds a non-finite value, else
+ *   LB_ERR_NEGATIVE_DENSITY if any node has a non-positive density (the
+ *   lattice has left the physical range: Ma too large for the forcing);
+ *   h_out is written in both cases.
  */
 int lb_diagnostics(lb_ctx* ctx, double* h_out);
 
 /* Wait for the stream; reports a pending device error or non-finite flag. */
 int lb_sync(lb_ctx* ctx);
+
+/*
+ * Checkpoint and resume.  The state of a context between steps - the current
+ * populations, the per-box records (FP16 exponents, counter-force), the FP16
+ * tile maxima, the thermal step counter, the non-finite flags and the binning
+ * windows of the points - is copied to or from a caller buffer (device or
+ * pinned host memory, 256-byte aligned, at least lb_checkpoint_bytes bytes;
+ * the copies are stream-ordered).  Point positions and forces stay the
+ * caller's arrays: save them alongside.  To resume, create a context with the
+ * same lb_params, register the same sets (same kinds, sizes and order, the
+ * saved positions) and call lb_checkpoint_load before stepping: the resumed
+ * run then continues bit for bit as the uninterrupted run would.
+ * lb_checkpoint_save needs the registered points to have been binned (a step,
+ * or lb_moments, since the sets last changed): LB_ERR_STATE otherwise.
+ * lb_checkpoint_load waits for the stream, checks the saved header against
+ * the context (LB_ERR_ARG on a mismatch) and sets lb_steps_taken to the saved
+ * count.
+ */
+int lb_checkpoint_bytes(const lb_ctx* ctx, size_t* bytes);
+int lb_checkpoint_save(lb_ctx* ctx, void* d_dst);
+int lb_checkpoint_load(lb_ctx* ctx, const void* d_src);
 
 /* Release the context (host memory and cached graphs); the workspace stays the caller's. */
 int lb_destroy(lb_ctx* ctx);
@@ -351,6 +379,7 @@ int lbml_loss_grad(const uint16_t* d_w16, int64_t n, const float* d_x, const flo
                    float* d_loss, float* d_work, void* hip_stream);
 int lbml_adam_step(float* d_master, float* d_m, float* d_v, const float* d_grad, uint16_t* d_w16, int32_t t,
                    float lr, float beta1, float beta2, float eps, void* hip_stream);
+
 
 #ifdef __cplusplus
 }

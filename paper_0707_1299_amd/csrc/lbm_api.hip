@@ -4,8 +4,8 @@
 // the two population copies (pull scheme, A/B), per-box parameters, the
 // per-point records, the tile bins and the scratch of the reductions, and
 // enqueues every kernel on the caller's stream.  Repeated steps are captured
-// once per (parity, force-set generation) into a HIP graph of two steps and
-// replayed.
+// once per (parity, force-set generation, length) into HIP graphs of 2, 4,
+// ..., 32 steps and replayed.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -49,7 +49,8 @@ int max_axis_tiles(int n, int t)
 }
 
 struct Layout {
-    size_t pop[2], boxes, rec, count, cursor, toff, bsum, tlist, tlist_tmp, partial, fpart, pmax, tmax, ticket, tctr,
+    size_t pop[2], boxes, rec, psum, count, cursor, toff, bsum, tlist, tlist_tmp, partial, fpart, pmax, tmax, ticket,
+        tctr,
         err, nf, rebin, rebox, win,
         diag, diagout;
     size_t total;
@@ -164,6 +165,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.pop[1] = take(popb);
     L.boxes = take(sizeof(BoxDev) * p->nboxes);
     L.rec = take(rec_bytes(p->storage) * P.cap);
+    L.psum = take(sizeof(double) * 3 * (prep_blocks(P.cap) + LB_MAX_SETS));
     L.count = take(sizeof(int) * G.ntiles);
     L.cursor = take(sizeof(int) * G.ntiles);
     L.toff = take(sizeof(int) * (G.ntiles + 1));
@@ -201,9 +203,23 @@ struct Set {
     lb_elastic el;   // KIND_ELASTIC only
 };
 
+// longest captured chunk of steps (a power of two; graphs of 2, 4, ..., GRAPH_MAX steps)
+constexpr int GRAPH_MAX = 32;
+
+// Header of a checkpoint (see lb_checkpoint_save): what the state was taken from, and where each
+// section starts in the blob.
+struct CkptHeader {
+    char magic[8];
+    int32_t nx, ny, nz, nboxes, storage, collision, tx, ty, tz, pad;
+    int64_t steps, npoints, pop_bytes, tiles, total;
+    int64_t off_pop, off_boxes, off_tmax, off_tctr, off_nf, off_win;
+};
+constexpr char CKPT_MAGIC[8] = {'l', 'b', 'c', 'k', 'p', 't', '0', '1'};
+
 struct GraphEntry {
     int parity;
     unsigned long long gen;
+    int len;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -230,12 +246,14 @@ struct lb_ctx {
     double timed_ms;
     long long timed_launches;
     long long steps;
+    CkptHeader ckpt;   // header of the last checkpoint taken (read by its stream-ordered copy)
     std::vector<BoxDev> hboxes;
     std::string err;
 
     void* pop(int k) const { return ws + P.L.pop[k]; }
     BoxDev* boxes() const { return (BoxDev*)(ws + P.L.boxes); }
     void* rec() const { return ws + P.L.rec; }
+    double* psum() const { return (double*)(ws + P.L.psum); }
     int* count() const { return (int*)(ws + P.L.count); }
     int* cursor() const { return (int*)(ws + P.L.cursor); }
     int* toff() const { return (int*)(ws + P.L.toff); }
@@ -305,15 +323,25 @@ void force_rebin(lb_ctx* c, hipStream_t s)
     c->binned_gen = c->gen;
 }
 
+// blocks of point-force sums the records kernel writes (one box only; see k_prep)
+long long npsum(const lb_ctx* c)
+{
+    long long nb = 0;
+    for (auto& s : c->sets) nb += prep_blocks(s.n);
+    return nb;
+}
+
 // records + tile bins for the current point positions (the binning kernels
 // rebuild the lists only while the rebuild flag is set)
 void build_points(lb_ctx* c, hipStream_t s)
 {
     const Geom& G = c->P.G;
-    long long off = 0;
+    long long off = 0, blk = 0;
     for (auto& st : c->sets) {
-        launch_prep(c->p.storage, G, st.n, off, st.pos, st.frc, st.box, c->rec(), c->errw(), s);
+        double* ps = G.nboxes == 1 ? c->psum() + 3 * blk : nullptr;
+        launch_prep(c->p.storage, G, st.n, off, st.pos, st.frc, st.box, c->rec(), c->errw(), ps, s);
         off += st.n;
+        blk += prep_blocks(st.n);
     }
     launch_bins(c->p.storage, G, off, c->rec(), c->count(), c->bsum(), c->toff(), c->cursor(), c->tlist(),
                 c->tlist_tmp(), s);
@@ -328,8 +356,10 @@ void box_update(lb_ctx* c, hipStream_t s, bool fp16_exp)
     const bool sums = c->p.zero_net_force != 0 && !c->gc_valid;
     const bool fp16 = fp16_exp && c->p.storage == LB_STORAGE_FP16;
     if (!sums && !fp16) return;
-    launch_box_update(c->p.storage, c->P.G, c->rec(), total_points(c) > 0 ? c->toff() : nullptr, c->tlist(), c->tmax(),
-                      c->fpart(), c->pmax(), c->ticket(), c->boxes(), sums ? 1 : 0, fp16 ? 1 : 0, s);
+    const bool one = c->P.G.nboxes == 1;
+    launch_box_update(c->p.storage, c->P.G, c->rec(), total_points(c) > 0 ? c->toff() : nullptr, c->tlist(),
+                      one ? c->psum() : nullptr, one ? npsum(c) : 0, c->tmax(), c->fpart(), c->pmax(), c->ticket(),
+                      c->boxes(), sums ? 1 : 0, fp16 ? 1 : 0, s);
     if (sums) c->gc_valid = true;
 }
 
@@ -425,10 +455,11 @@ void drop_graphs(lb_ctx* c)
     c->graphs.clear();
 }
 
-int get_graph(lb_ctx* c, bool rebuild, hipGraphExec_t* out)
+// graph of len (even) steps from the current parity; captured on first use
+int get_graph(lb_ctx* c, bool rebuild, int len, hipGraphExec_t* out)
 {
     for (auto& g : c->graphs)
-        if (g.parity == c->cur && g.gen == c->gen) {
+        if (g.parity == c->cur && g.gen == c->gen && g.len == len) {
             *out = g.exec;
             return LB_OK;
         }
@@ -439,8 +470,7 @@ int get_graph(lb_ctx* c, bool rebuild, hipGraphExec_t* out)
     const int parity = c->cur;
     int r = hip_check(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
     if (r) return r;
-    enqueue_step(c, c->cap_stream, rebuild);
-    enqueue_step(c, c->cap_stream, rebuild);
+    for (int k = 0; k < len; ++k) enqueue_step(c, c->cap_stream, rebuild);   // len even: parity restored
     hipGraph_t graph;
     r = hip_check(c, hipStreamEndCapture(c->cap_stream, &graph), "hipStreamEndCapture");
     if (r) return r;
@@ -450,7 +480,7 @@ int get_graph(lb_ctx* c, bool rebuild, hipGraphExec_t* out)
         (void)hipGraphDestroy(graph);
         return r;
     }
-    c->graphs.push_back({parity, c->gen, graph, exec});
+    c->graphs.push_back({parity, c->gen, len, graph, exec});
     *out = exec;
     return LB_OK;
 }
@@ -707,14 +737,20 @@ int lb_step(lb_ctx* c, int32_t nsteps)
     if (c->timing || left < 4) {
         for (int k = 0; k < left; ++k) enqueue_step(c, c->stream, rebuild);
     } else {
-        hipGraphExec_t exec;
-        int r = get_graph(c, rebuild, &exec);
-        if (r) return r;
-        for (int k = 0; k + 1 < left; k += 2) {
-            r = hip_check(c, hipGraphLaunch(exec, c->stream), "hipGraphLaunch");
+        // the longest power-of-two chunks first
+        int rest = left;
+        while (rest >= 2) {
+            int len = GRAPH_MAX;
+            while (len > rest) len >>= 1;
+            hipGraphExec_t exec;
+            int r = get_graph(c, rebuild, len, &exec);
             if (r) return r;
+            for (; rest >= len; rest -= len) {
+                r = hip_check(c, hipGraphLaunch(exec, c->stream), "hipGraphLaunch");
+                if (r) return r;
+            }
         }
-        if (left & 1) enqueue_step(c, c->stream, rebuild);
+        if (rest) enqueue_step(c, c->stream, rebuild);
     }
     c->steps += left;
     return check_async(c);
@@ -802,7 +838,12 @@ int lb_diagnostics(lb_ctx* c, double* h_out)
                                  c->stream),
                   "hipMemcpy");
     if (r) return r;
-    return read_flags(c);
+    r = read_flags(c);   // waits for the copy
+    if (r) return r;
+    for (int b = 0; b < c->p.nboxes; ++b)
+        if (h_out[(size_t)b * LBD_N + 12] > 0.0)
+            return fail(c, LB_ERR_NEGATIVE_DENSITY, "non-positive density in box " + std::to_string(b));
+    return LB_OK;
 }
 
 int lb_sync(lb_ctx* c)
@@ -811,6 +852,102 @@ int lb_sync(lb_ctx* c)
     int r = check_async(c);
     if (r) return r;
     return read_flags(c);
+}
+
+static CkptHeader ckpt_layout(const lb_ctx* c)
+{
+    CkptHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, CKPT_MAGIC, 8);
+    const Geom& G = c->P.G;
+    h.nx = G.nx; h.ny = G.ny; h.nz = G.nz; h.nboxes = G.nboxes;
+    h.storage = c->p.storage; h.collision = c->p.collision;
+    h.tx = G.tx; h.ty = G.ty; h.tz = G.tz;
+    h.steps = c->steps;
+    h.npoints = total_points(c);
+    h.pop_bytes = (int64_t)G.sbox * G.nboxes * (int64_t)storage_bytes(c->p.storage);
+    h.tiles = G.ntiles;
+    size_t o = align_up(sizeof(CkptHeader));
+    auto take = [&](size_t b) { const size_t at = o; o = align_up(o + std::max<size_t>(b, 1)); return (int64_t)at; };
+    h.off_pop = take(h.pop_bytes);
+    h.off_boxes = take(sizeof(BoxDev) * G.nboxes);
+    h.off_tmax = take(sizeof(float) * G.ntiles);
+    h.off_tctr = take(sizeof(unsigned long long));
+    h.off_nf = take(sizeof(int) * G.nboxes);
+    h.off_win = take(sizeof(int4) * std::max<long long>(h.npoints, 1));
+    h.total = (int64_t)o;
+    return h;
+}
+
+int lb_checkpoint_bytes(const lb_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LB_ERR_ARG;
+    *bytes = (size_t)ckpt_layout(c).total;
+    return LB_OK;
+}
+
+int lb_checkpoint_save(lb_ctx* c, void* dst)
+{
+    if (!c) return LB_ERR_ARG;
+    clear_stale_error();
+    if (!dst || ((uintptr_t)dst % ALIGN) != 0) return fail(c, LB_ERR_ARG, "checkpoint buffer NULL or not 256-byte aligned");
+    // the binning windows are part of the state once the registered sets have been binned
+    if (total_points(c) > 0 && c->binned_gen != c->gen)
+        return fail(c, LB_ERR_STATE, "checkpoint: step once after changing the point sets");
+    c->ckpt = ckpt_layout(c);
+    const CkptHeader& h = c->ckpt;
+    char* d = (char*)dst;
+    hipStream_t s = c->stream;
+    int r = LB_OK;
+    auto cp = [&](int64_t off, const void* src, size_t n) {
+        if (!r) r = hip_check(c, hipMemcpyAsync(d + off, src, n, hipMemcpyDefault, s), "checkpoint copy");
+    };
+    cp(0, &c->ckpt, sizeof(CkptHeader));
+    cp(h.off_pop, c->pop(c->cur), (size_t)h.pop_bytes);
+    cp(h.off_boxes, c->boxes(), sizeof(BoxDev) * c->p.nboxes);
+    cp(h.off_tmax, c->tmax(), sizeof(float) * c->P.G.ntiles);
+    cp(h.off_tctr, c->tctr() + c->cur, sizeof(unsigned long long));
+    cp(h.off_nf, c->nf(), sizeof(int) * c->p.nboxes);
+    if (h.npoints > 0) cp(h.off_win, c->win(), sizeof(int4) * h.npoints);
+    return r ? r : check_async(c);
+}
+
+int lb_checkpoint_load(lb_ctx* c, const void* src)
+{
+    if (!c) return LB_ERR_ARG;
+    clear_stale_error();
+    if (!src || ((uintptr_t)src % ALIGN) != 0) return fail(c, LB_ERR_ARG, "checkpoint buffer NULL or not 256-byte aligned");
+    CkptHeader h;
+    int r = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (!r) r = hip_check(c, hipMemcpy(&h, src, sizeof(h), hipMemcpyDefault), "checkpoint header");
+    if (r) return r;
+    const CkptHeader want = ckpt_layout(c);
+    if (memcmp(h.magic, CKPT_MAGIC, 8) != 0) return fail(c, LB_ERR_ARG, "not a checkpoint");
+    if (h.nx != want.nx || h.ny != want.ny || h.nz != want.nz || h.nboxes != want.nboxes ||
+        h.storage != want.storage || h.collision != want.collision || h.tx != want.tx || h.ty != want.ty ||
+        h.tz != want.tz || h.npoints != want.npoints || h.total != want.total)
+        return fail(c, LB_ERR_ARG, "checkpoint of another lattice, tiling or point count");
+    const char* d = (const char*)src;
+    hipStream_t s = c->stream;
+    auto cp = [&](void* dst, int64_t off, size_t n) {
+        if (!r) r = hip_check(c, hipMemcpyAsync(dst, d + off, n, hipMemcpyDefault, s), "checkpoint copy");
+    };
+    cp(c->pop(c->cur), h.off_pop, (size_t)h.pop_bytes);
+    cp(c->boxes(), h.off_boxes, sizeof(BoxDev) * c->p.nboxes);
+    cp(c->tmax(), h.off_tmax, sizeof(float) * c->P.G.ntiles);
+    cp(c->tctr() + c->cur, h.off_tctr, sizeof(unsigned long long));
+    cp(c->nf(), h.off_nf, sizeof(int) * c->p.nboxes);
+    if (h.npoints > 0) cp(c->win(), h.off_win, sizeof(int4) * h.npoints);
+    if (r) return r;
+    // rebuild the tile lists at the next step with the saved windows: the lists flag raised,
+    // no box choosing new windows unless one of its points has left its window
+    launch_fill_u32(c->rebin(), 1, 1u, s);
+    launch_fill_u32(c->rebox(), c->p.nboxes, 0u, s);
+    c->binned_gen = c->gen;
+    c->bins_valid = false;
+    c->gc_valid = false;
+    c->steps = h.steps;
+    return check_async(c);
 }
 
 int lb_destroy(lb_ctx* c)
@@ -834,6 +971,7 @@ const char* lb_status_string(int status)
     case LB_ERR_NONFINITE: return "non-finite value detected";
     case LB_ERR_CAPACITY: return "capacity exceeded";
     case LB_ERR_STATE: return "invalid state";
+    case LB_ERR_NEGATIVE_DENSITY: return "non-positive density";
     }
     return "unknown status";
 }

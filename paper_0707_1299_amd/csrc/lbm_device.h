@@ -411,15 +411,15 @@ __device__ __forceinline__ void pull_pairs(const _Float16* __restrict__ sb, long
 }
 
 // The 19 pre-collision populations of node (x, y, z) as deviations (for FP16
-// storage: deviation / w_i in units of the stored scale), pulled from the
-// post-collision data of the upstream nodes x - c_i.  xm/xp etc. are the
-// periodic neighbours of x, y, z.  The populations layout reads one value per
+// storage the stored (deviation / w_i) 2^e times w_i sc, sc = 2^-e for the
+// deviation itself), pulled from the post-collision data of the upstream nodes
+// x - c_i.  xm/xp etc. are the periodic neighbours of x, y, z.  The populations layout reads one value per
 // direction; the moment layout rebuilds each population from the upstream
 // node's stored bracket pieces.
 template <int ST, bool NTL, int ADDR>
 __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restrict__ sb, long long rb, long long kp,
                                           unsigned box_bytes, int ny, int x, int y, int z, int xm, int xp, int ym,
-                                          int yp, int zm, int zp, typename StoreT<ST>::T (&f)[NQ])
+                                          int yp, int zm, int zp, typename StoreT<ST>::T (&f)[NQ], float sc = 1.0f)
 {
     using S = typename StoreT<ST>::S;
     using T = typename StoreT<ST>::T;
@@ -443,7 +443,7 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
             if (cy * cz != 0) br += cy * cz > 0 ? piece(MP_BYZ) : -piece(MP_BYZ);
             f[i] = T(wgt(i)) * br;
         } else if constexpr (ST == ST_FP16) {
-            f[i] = fp16_in(load_pop<S, NTL, ADDR>(sb, rb, kp, box_bytes, i, row, sx), float(wgt(i)));
+            f[i] = fp16_in(load_pop<S, NTL, ADDR>(sb, rb, kp, box_bytes, i, row, sx), float(wgt(i)) * sc);
         } else {
             f[i] = piece(i);
         }

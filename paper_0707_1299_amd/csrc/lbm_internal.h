@@ -8,7 +8,7 @@
 
 namespace lbm {
 
-constexpr int LBD_N = 12;               // diagnostics per box
+constexpr int LBD_N = 13;               // diagnostics per box
 constexpr int LBML_NPARAM_DEV = 4545;   // MLP parameters
 
 struct AdvectLaunch {
@@ -49,16 +49,16 @@ void launch_equilibrium(int storage, const Geom& G, void* dst, const BoxDev* box
                         const double* u, hipStream_t s);
 
 void launch_fill_u32(void* p, long long n, uint32_t v, hipStream_t s);
+long long prep_blocks(long long n);
 void launch_prep(int storage, const Geom& G, long long n, long long off, const double* pos, const double* frc,
-                 const int* boxid, void* rec, int* err, hipStream_t s);
+                 const int* boxid, void* rec, int* err, double* psum, hipStream_t s);
 long long scan_blocks(long long ntiles);
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
                  int* cursor, int* tlist, int* tlist_tmp, hipStream_t s);
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
-                       const float* tmax, double* part, float* pmax, unsigned* ticket, BoxDev* boxes, int zero_net,
-                       int fp16_exp, hipStream_t s);
-void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial,
-                   hipStream_t s);
+                       const double* psum, long long npsum, const float* tmax, double* part, float* pmax,
+                       unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s);
+void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial, hipStream_t s);
 void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,
                           const void* src, const BoxDev* boxes, const int* toff, const int* tlist, const void* rec,
                           hipStream_t s);

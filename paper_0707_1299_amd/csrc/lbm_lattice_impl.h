@@ -93,19 +93,23 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const unsigned box_bytes = unsigned(G.sbox * (long long)sizeof(S));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     [[maybe_unused]] uint32_t wpair[NPL == 2 ? NQ : 1];
+    // FP16: stored values are (deviation / w_i) 2^e; the conversion multiplies by w_i 2^-e (exact:
+    // a power of two times w_i), so the moments come out in deviation units
+    [[maybe_unused]] const float sc = ST == ST_FP16 ? (MODE == M_STEP ? B.s_in : ldexpf(1.0f, -B.e_data)) : 1.0f;
     T f[NQ];
     if constexpr (NPL == 2) {
         const int xl = x == 0 ? G.nx - 2 : x - 2, xr = x + 2 == G.nx ? 0 : x + 2;
         pull_pairs<LX, NTL, ADDR>(reinterpret_cast<const _Float16*>(sb), G.rb, G.kp, box_bytes, G.ny, G.nx, x, xl, xr,
                                   y, z, ym, yp, zm, zp, wpair);
     } else {
-        pull_node<ST, NTL, ADDR>(sb, G.rb, G.kp, box_bytes, G.ny, x, y, z, xm, xp, ym, yp, zm, zp, f);
+        pull_node<ST, NTL, ADDR>(sb, G.rb, G.kp, box_bytes, G.ny, x, y, z, xm, xp, ym, yp, zm, zp, f, sc);
     }
 
     int k0 = 0, k1 = 0;         // the tile's entries in the point lists (read below)
     S* db = dst + (long long)box * G.sbox;
     const unsigned row = unsigned(z) * unsigned(G.ny) + unsigned(y);
-    [[maybe_unused]] uint32_t opair[NPL == 2 ? NQ : 1];
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    [[maybe_unused]] half2_t opair[NPL == 2 ? NQ : 1];
     bool bad = false;
     T mx = 0;                     // FP16: largest |f*_i / w_i| of the lane's nodes
     T uxs[NPL], uys[NPL], uzs[NPL];
@@ -119,7 +123,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 const uint32_t bits = h == 0 ? (wpair[i] & 0xffffu) : (wpair[i] >> 16);
-                f[i] = fp16_in(__builtin_bit_cast(_Float16, uint16_t(bits)), float(wgt(i)));
+                f[i] = fp16_in(__builtin_bit_cast(_Float16, uint16_t(bits)), float(wgt(i)) * sc);
             }
         }
 
@@ -137,11 +141,6 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             if (cx * cy != 0) pxy += cx * cy > 0 ? sm : -sm;
             if (cx * cz != 0) pxz += cx * cz > 0 ? sm : -sm;
             if (cy * cz != 0) pyz += cy * cz > 0 ? sm : -sm;
-        }
-        if constexpr (ST == ST_FP16) {
-            const T s = MODE == M_STEP ? T(B.s_in) : T(ldexpf(1.0f, -B.e_data));
-            drho *= s; jx *= s; jy *= s; jz *= s;
-            pxx *= s; pyy *= s; pzz *= s; pxy *= s; pxz *= s; pyz *= s;
         }
 
         // ---- force density at this node: counter-force + the tile's points
@@ -166,7 +165,12 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         }
 
         const T rho = T(G.rho0) + drho;
-        const T ir = T(1) / rho;
+        // FP16 storage: the hardware reciprocal (1 ulp), far below the storage's rounding
+        T ir;
+        if constexpr (ST == ST_FP16)
+            ir = __builtin_amdgcn_rcpf(rho);
+        else
+            ir = T(1) / rho;
         const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
 
         if constexpr (MODE == M_MOMENTS) {
@@ -192,6 +196,8 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             v[9] = X * double(gy) - Y * double(gx);
             v[10] = sqrt(double(ux) * ux + double(uy) * uy + double(uz) * uz);
             v[11] = nonfin ? 1.0 : 0.0;
+            v[12] = rho > T(0) ? 0.0 : 1.0;   // non-positive density (NaN counts under 11, not here)
+            if (nonfin) v[12] = 0.0;
             __shared__ double red[4][LBD_N];
 #pragma unroll
             for (int c = 0; c < LBD_N; ++c) {
@@ -228,8 +234,6 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             // populations are dead before the collision
             const T kg = T(B.kappa_g);
             const T hbase = drho - T(1.5) * (sxx + syy + szz);
-            T s_in = T(1);
-            if constexpr (ST == ST_FP16) s_in = T(B.s_in);
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
@@ -242,7 +246,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                 if (cy * cz != 0) q += cy * cz > 0 ? T(2) * pyz : T(-2) * pyz;
                 const T hb = hbase + T(3) * a + T(4.5) * q;
                 const T inv_w = i == 0 ? T(3) : (cx * cx + cy * cy + cz * cz == 1 ? T(18) : T(36));
-                br[i] = kg * (f[i] * s_in * inv_w - hb);
+                br[i] = kg * (f[i] * inv_w - hb);
             }
         }
         const T tau = T(B.tau), om = T(B.omega);
@@ -267,13 +271,20 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
         const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
         const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
-        T base = drho - T(1.5) * (Bxx + Byy + Bzz);
+        // FP16, two nodes per lane, projected operator: the pieces below carry the output scale 2^e
+        // (exact), so the rebuilt brackets are the values to round and each pair of nodes is
+        // converted by one packing conversion without a multiply (one node per lane converts
+        // with a mixed-precision multiply, where the scale costs nothing)
+        constexpr bool FOLD = ST == ST_FP16 && COLL == 0 && NPL == 2;
+        const T so = FOLD ? T(B.s_out) : T(1);
+        T base = FOLD ? so * drho - (T(1.5) * so) * (Bxx + Byy + Bzz) : drho - T(1.5) * (Bxx + Byy + Bzz);
 
         // f*_i / w_i = base + c_i.(3A) + sum_a c_ia^2 (9/2) B_aa + sum_{a<b} c_ia c_ib 9 B_ab: for an
         // opposite pair the even part is shared and the odd part (3A.c_i) changes sign
-        const T a3x = T(3) * ax, a3y = T(3) * ay, a3z = T(3) * az;
-        T bxx = T(4.5) * Bxx, byy = T(4.5) * Byy, bzz = T(4.5) * Bzz;
-        T bxy = T(9) * Bxy, bxz = T(9) * Bxz, byz = T(9) * Byz;
+        const T a3x = (T(3) * so) * ax, a3y = (T(3) * so) * ay, a3z = (T(3) * so) * az;
+        T bxx = (T(4.5) * so) * Bxx, byy = (T(4.5) * so) * Byy, bzz = (T(4.5) * so) * Bzz;
+        T bxy = (T(9) * so) * Bxy, bxz = (T(9) * so) * Bxz, byz = (T(9) * so) * Byz;
+        [[maybe_unused]] const float s_store = FOLD ? 1.0f : B.s_out;   // scale still to apply at the store
 
         // thermal increment w_i sum_k e_k(c_i) phi_k / b_k, <phi_k^2> = mu rho b_k (1 - gamma_k^2), in
         // units of w_i: amp[k] = phi_k / b_k.  Philox call j gives the normals of modes 4j .. 4j+3.
@@ -348,7 +359,9 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 
         // ---- health of this node: non-finite moments or forces
         {
-            const T chk = drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
+            // FP16 populations are bounded (|stored| <= 65504), so a non-finite one always reaches drho;
+            // the other storages also check the sums that could overflow on their own
+            const T chk = ST == ST_FP16 ? drho + gx + gy + gz : drho + jx + jy + jz + pxx + pyy + pzz + gx + gy + gz;
             bad = bad || (valid && !(fabs(chk) <= T(sizeof(T) == 4 ? 3.0e38 : 1.0e300)));
         }
 
@@ -356,8 +369,10 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         if constexpr (NPL == 2) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
-                const uint32_t bits = __builtin_bit_cast(uint16_t, fp16_out(br[i], B.s_out));
-                opair[i] = h == 0 ? bits : (opair[i] | (bits << 16));
+                if (h == 0)
+                    opair[i].x = fp16_out(br[i], s_store);
+                else
+                    opair[i].y = fp16_out(br[i], s_store);
             }
         } else if (valid) {
             if constexpr (ST == ST_MOM32) {
@@ -369,7 +384,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                 for (int i = 0; i < NQ; ++i) {
                     S v;
                     if constexpr (ST == ST_FP16)
-                        v = fp16_out(br[i], B.s_out);
+                        v = fp16_out(br[i], s_store);
                     else
                         v = S(T(wgt(i)) * br[i]);
                     store_pop<S, ADDR>(v, db, G.rb, G.kp, box_bytes, i, row, x);
@@ -377,7 +392,8 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             }
         }
 
-        // ---- FP16: the largest stored magnitude, for the range check and the rescaling
+        // ---- FP16: the largest bracket magnitude (with FOLD already times 2^e), for the range
+        // check and the rescaling
         if constexpr (ST == ST_FP16) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) mx = fmax(mx, fabs(br[i]));
@@ -391,12 +407,14 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         if (valid) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i)
-                store_pair<ADDR>(opair[i], reinterpret_cast<_Float16*>(db), G.rb, G.kp, box_bytes, i, row, x);
+                store_pair<ADDR>(__builtin_bit_cast(uint32_t, opair[i]), reinterpret_cast<_Float16*>(db), G.rb, G.kp,
+                                 box_bytes, i, row, x);
         }
     }
     if constexpr (ST == ST_FP16) {
+        constexpr bool FOLD = COLL == 0 && NPL == 2;
         T m = valid ? mx : T(0);
-        bad = bad || (m * B.s_out > T(65504));
+        bad = bad || ((FOLD ? m : m * B.s_out) > T(65504));
         m = wave_max(m);
         __shared__ float wm[NW];
         if (lane == 0) wm[wave] = m;
@@ -406,7 +424,8 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             float t = wm[0];
 #pragma unroll
             for (int q = 1; q < NW; ++q) t = fmaxf(t, wm[q]);
-            ((float*)out1)[tile] = t;
+            // the largest |f*_i / w_i| of the tile, without the scale (1 / 2^e is exact)
+            ((float*)out1)[tile] = FOLD ? t * (1.0f / B.s_out) : t;
         }
         __syncthreads();   // wm is rewritten by the block's next tile
     }
@@ -438,6 +457,12 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             if (gz >= G.nz) gz -= G.nz;
             const int lx2 = gx - x0, ly2 = gy - y0, lz2 = gz - z0;
             const bool in = unsigned(lx2) < unsigned(TX) && unsigned(ly2) < unsigned(TY) && unsigned(lz2) < unsigned(TZ);
+            double* o = out0 + ((long long)pk_point(ent) * G.maxp + pk_slot(ent)) * 3;
+            // a tile of the point's window that holds no node of its stencil: its partial is zero
+            if (!__any(in)) {
+                if (lane == 0) o[0] = o[1] = o[2] = 0.0;
+                continue;
+            }
             const int li = in ? lx2 + TX * (ly2 + TY * lz2) : 0;
             const T w = in ? r.wx[dx] * r.wy[dy] * r.wz[dz] : T(0);
             const T sx = wave_sum(su[0][li] * w);
@@ -445,7 +470,6 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             const T sz = wave_sum(su[2][li] * w);
             if (lane == 0) {
                 // the point's partial for this tile, in its own slot (point-major layout)
-                double* o = out0 + ((long long)pk_point(ent) * G.maxp + pk_slot(ent)) * 3;
                 o[0] = double(sx);
                 o[1] = double(sy);
                 o[2] = double(sz);

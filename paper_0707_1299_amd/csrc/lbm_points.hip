@@ -10,6 +10,8 @@
 // integrated with one explicit Euler step per lattice step.
 #include <math.h>
 
+#include <algorithm>
+
 #include "lbm_device.h"
 #include "lbm_internal.h"
 #include "lbm_noise.h"
@@ -127,14 +129,42 @@ int lanes_per_point(int maxp)
 // ---------------------------------------------------------------------------
 // 1. records: wrapped base node, one-dimensional weights, force (one thread per
 //    point).  err bit 1: box id out of range, bit 2: non-finite input.
+//    With psum set (one box), each block also writes the sum of its points'
+//    forces (as the records hold them) to psum[blockIdx.x]: the counter-force
+//    then needs no pass over the tile lists.
+template <class T>
+__device__ __forceinline__ void prep_point(const Geom& G, long long i, long long p, const double* __restrict__ pos,
+                                           const double* __restrict__ frc, const int* __restrict__ boxid,
+                                           PRec<T>* __restrict__ rec, int* __restrict__ err, double (&fs)[3]);
+
 template <class T>
 __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long long off, const double* __restrict__ pos,
                                               const double* __restrict__ frc, const int* __restrict__ boxid,
-                                              PRec<T>* __restrict__ rec, int* __restrict__ err)
+                                              PRec<T>* __restrict__ rec, int* __restrict__ err,
+                                              double* __restrict__ psum)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const long long p = off + i;
+    double fs[3] = {0.0, 0.0, 0.0};
+    if (i < n) prep_point<T>(G, i, off + i, pos, frc, boxid, rec, err, fs);
+    if (!psum) return;
+    __shared__ double red[4][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = 0; k < 3; ++k) {
+        const double v = wave_sum(fs[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        psum[3 * (long long)blockIdx.x + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void prep_point(const Geom& G, long long i, long long p, const double* __restrict__ pos,
+                                           const double* __restrict__ frc, const int* __restrict__ boxid,
+                                           PRec<T>* __restrict__ rec, int* __restrict__ err, double (&fs)[3])
+{
     int box = boxid ? boxid[i] : 0;
     if (box < 0 || box >= G.nboxes) {
         atomicOr(err, 1);
@@ -171,6 +201,7 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
     r.f[2] = T(F[2]);
     r.pad = T(0);
     rec[p] = r;
+    for (int a = 0; a < 3; ++a) fs[a] = double(r.f[a]);
     // skin crossing: the stencil has left the window it was binned with
     const int4 w = G.win[p];
     // (flags read first: after a change of the sets every point is outside its window and
@@ -186,26 +217,32 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
 //    of slot k.  Windows are chosen afresh (lane 0 stores them) only for the points of
 //    boxes in which a point crossed; the others keep theirs, so what a box computes
 //    never depends on crossings in the other boxes of a batch.
+//    The binning kernels of steps 1b-4 run a capped grid that strides over the work:
+//    in the usual step (no crossing) they only read the flag, and a small grid
+//    does that in little more than the launch.
+constexpr unsigned BIN_GRID = 256;
+
 template <class T>
-__global__ __launch_bounds__(256) void k_count(const Geom G, long long n, long long off, int gp,
-                                               const PRec<T>* __restrict__ rec, int* __restrict__ count)
+__global__ __launch_bounds__(256) void k_count(const Geom G, long long n, int gp, const PRec<T>* __restrict__ rec,
+                                               int* __restrict__ count)
 {
     if (!*G.rebin) return;
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long i = gid / gp;
-    const int k = int(gid % gp);
-    if (i >= n || k >= G.maxp) return;
-    const long long p = off + i;
-    const PRec<T> r = rec[p];
-    const bool fresh = G.rebox[r.box] != 0;
-    const int4 w = fresh ? make_int4(window_base(r.bx, G.nx, r.wx), window_base(r.by, G.ny, r.wy),
-                                     window_base(r.bz, G.nz, r.wz), r.box)
-                         : G.win[p];
-    if (fresh && k == 0) G.win[p] = w;
-    TileSet s;
-    window_tiles(G, w.x, w.y, w.z, s);
-    const long long t = slot_tile(G, s, r.box, k);
-    if (t >= 0) atomicAdd(&count[t], 1);
+    const long long total = n * gp, stride = (long long)gridDim.x * blockDim.x;
+    for (long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += stride) {
+        const long long p = gid / gp;
+        const int k = int(gid % gp);
+        if (k >= G.maxp) continue;
+        const PRec<T> r = rec[p];
+        const bool fresh = G.rebox[r.box] != 0;
+        const int4 w = fresh ? make_int4(window_base(r.bx, G.nx, r.wx), window_base(r.by, G.ny, r.wy),
+                                         window_base(r.bz, G.nz, r.wz), r.box)
+                             : G.win[p];
+        if (fresh && k == 0) G.win[p] = w;
+        TileSet s;
+        window_tiles(G, w.x, w.y, w.z, s);
+        const long long t = slot_tile(G, s, r.box, k);
+        if (t >= 0) atomicAdd(&count[t], 1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -242,16 +279,22 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total)
     return r;
 }
 
+// Chunks of SCAN_B counts; block b of the (capped) grid takes chunks b, b + grid, ...
+constexpr unsigned SCAN_GRID = 16;
+
 __global__ __launch_bounds__(SCAN_B) void k_scan_sums(long long n, const int* __restrict__ count, int* __restrict__ bsum,
                                                       const int* __restrict__ rebin)
 {
     if (!*rebin) return;
     __shared__ int sh[SCAN_B / 64 + 1];
-    const long long i = (long long)blockIdx.x * SCAN_B + threadIdx.x;
-    const int v = i < n ? count[i] : 0;
-    int total;
-    block_exclusive_scan(v, sh, total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+    const long long nch = (n + SCAN_B - 1) / SCAN_B;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        const long long i = c * SCAN_B + threadIdx.x;
+        const int v = i < n ? count[i] : 0;
+        int total;
+        block_exclusive_scan(v, sh, total);
+        if (threadIdx.x == 0) bsum[c] = total;
+    }
 }
 
 __global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restrict__ count, const int* __restrict__ bsum,
@@ -260,25 +303,24 @@ __global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restr
 {
     if (!*rebin) return;
     __shared__ int sh[SCAN_B / 64 + 1];
-    __shared__ int pre;
-    // prefix of the block sums before this block
-    int acc = 0;
-    for (int b = threadIdx.x; b < (int)blockIdx.x; b += SCAN_B) acc += bsum[b];
-    int dummy;
-    const int part = block_exclusive_scan(acc, sh, dummy);
-    (void)part;
-    if (threadIdx.x == 0) pre = dummy;
-    __syncthreads();
-    const long long i = (long long)blockIdx.x * SCAN_B + threadIdx.x;
-    const int v = i < n ? count[i] : 0;
-    int total;
-    const int ex = block_exclusive_scan(v, sh, total);
-    if (i < n) {
-        toff[i] = pre + ex;
-        count[i] = 0;
-        cursor[i] = 0;
+    const long long nch = (n + SCAN_B - 1) / SCAN_B;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        // prefix of the chunk sums before this chunk
+        int acc = 0;
+        for (long long b = threadIdx.x; b < c; b += SCAN_B) acc += bsum[b];
+        int pre;
+        block_exclusive_scan(acc, sh, pre);
+        const long long i = c * SCAN_B + threadIdx.x;
+        const int v = i < n ? count[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, sh, total);
+        if (i < n) {
+            toff[i] = pre + ex;
+            count[i] = 0;
+            cursor[i] = 0;
+        }
+        if (c == nch - 1 && threadIdx.x == 0) toff[n] = pre + total;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) toff[n] = pre + total;
 }
 
 // ---------------------------------------------------------------------------
@@ -289,24 +331,26 @@ __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int 
                                               int* __restrict__ cursor, int* __restrict__ tlist)
 {
     if (!*G.rebin) return;
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (long long b = gid; b < G.nboxes; b += (long long)gridDim.x * blockDim.x) G.rebox[b] = 0;
-    const long long p = gid / gp;
-    const int k = int(gid % gp);
-    if (p >= npts) return;
-    const int4 w = G.win[p];
-    TileSet s;
-    window_tiles(G, w.x, w.y, w.z, s);
-    const long long t = slot_tile(G, s, w.w, k);
-    if (t < 0) return;
-    // home tile: the one holding the window's centre node (always inside the stencil)
-    int cx = w.x + 2, cy = w.y + 2, cz = w.z + 2;
-    if (cx >= G.nx) cx -= G.nx;
-    if (cy >= G.ny) cy -= G.ny;
-    if (cz >= G.nz) cz -= G.nz;
-    const bool home = t == tile_id(G, w.w, cz / G.tz, cy / G.ty, cx / G.tx);
-    const int slot = toff[t] + atomicAdd(&cursor[t], 1);
-    tlist[slot] = int(p << PK_SHIFT) | (home ? PK_HOME : 0) | k;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long gid0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long b = gid0; b < G.nboxes; b += stride) G.rebox[b] = 0;
+    for (long long gid = gid0; gid < npts * gp; gid += stride) {
+        const long long p = gid / gp;
+        const int k = int(gid % gp);
+        const int4 w = G.win[p];
+        TileSet s;
+        window_tiles(G, w.x, w.y, w.z, s);
+        const long long t = slot_tile(G, s, w.w, k);
+        if (t < 0) continue;
+        // home tile: the one holding the window's centre node (always inside the stencil)
+        int cx = w.x + 2, cy = w.y + 2, cz = w.z + 2;
+        if (cx >= G.nx) cx -= G.nx;
+        if (cy >= G.ny) cy -= G.ny;
+        if (cz >= G.nz) cz -= G.nz;
+        const bool home = t == tile_id(G, w.w, cz / G.tz, cy / G.ty, cx / G.tx);
+        const int slot = toff[t] + atomicAdd(&cursor[t], 1);
+        tlist[slot] = int(p << PK_SHIFT) | (home ? PK_HOME : 0) | k;
+    }
 }
 
 // 4. sort every tile's list by point index (so sums run in a fixed order).  One
@@ -317,18 +361,19 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_
                                                     const int* __restrict__ tin, int* __restrict__ tout)
 {
     if (!*G.rebin) return;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= max_entries || e >= toff[G.ntiles]) return;
-    const int v = tin[e];
-    const int p = pk_point(v), k = pk_slot(v);
-    const int4 w = G.win[p];
-    TileSet s;
-    window_tiles(G, w.x, w.y, w.z, s);
-    const long long t = slot_tile(G, s, w.w, k);
-    const int a = toff[t], b = toff[t + 1];
-    int rank = 0;
-    for (int j = a; j < b; ++j) rank += tin[j] < v ? 1 : 0;
-    tout[a + rank] = v;
+    const long long n = min(max_entries, (long long)toff[G.ntiles]);
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const int v = tin[e];
+        const int p = pk_point(v), k = pk_slot(v);
+        const int4 w = G.win[p];
+        TileSet s;
+        window_tiles(G, w.x, w.y, w.z, s);
+        const long long t = slot_tile(G, s, w.w, k);
+        const int a = toff[t], b = toff[t + 1];
+        int rank = 0;
+        for (int j = a; j < b; ++j) rank += tin[j] < v ? 1 : 0;
+        tout[a + rank] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -338,10 +383,13 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_
 //    once, at its home entry (flagged when the lists are built), striding over
 //    the box's own span of the lists in a fixed chunking, so the result does not
 //    depend on the other boxes that share the launch or on the order in which
-//    the bins were filled.
+//    the bins were filled.  With one box the records kernel has already summed
+//    the forces per block of points (psum, npsum blocks): those sums are added
+//    instead, in block order.
 template <class T>
 __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>* __restrict__ rec,
                                                     const int* __restrict__ toff, const int* __restrict__ tlist,
+                                                    const double* __restrict__ psum, long long npsum,
                                                     const float* __restrict__ tmax, double* __restrict__ part,
                                                     float* __restrict__ pmax, unsigned* __restrict__ ticket,
                                                     BoxDev* __restrict__ boxes, int zero_net, int fp16_exp)
@@ -355,7 +403,10 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
     if (fp16_exp)
         for (long long u = t; u < G.tiles_per_box; u += (long long)C * blockDim.x)
             m = fmaxf(m, tmax[(long long)b * G.tiles_per_box + u]);
-    if (zero_net && toff) {
+    if (zero_net && psum) {
+        for (long long u = t; u < npsum; u += (long long)C * blockDim.x)
+            for (int k = 0; k < 3; ++k) s[k] += psum[3 * u + k];
+    } else if (zero_net && toff) {
         const long long e0 = toff[(long long)b * G.tiles_per_box], e1 = toff[(long long)(b + 1) * G.tiles_per_box];
         const long long S = (long long)C * blockDim.x;
         // the thread's entries e0 + t + S j in increasing j, eight at a time: all list loads,
@@ -463,33 +514,6 @@ struct AdvectArgs {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-// 4 -> 64 tanh -> 64 tanh -> 1 with the weights staged in LDS as FP32
-__device__ float mlp_eval(const float* __restrict__ W, const float (&xin)[4])
-{
-    const float* W1 = W;
-    const float* b1 = W1 + 256;
-    const float* W2 = b1 + 64;
-    const float* b2 = W2 + 4096;
-    const float* W3 = b2 + 64;
-    const float* b3 = W3 + 64;
-    float h1[64];
-#pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        float s = b1[j];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s = fmaf(W1[j * 4 + k], xin[k], s);
-        h1[j] = tanhf(s);
-    }
-    float y = b3[0];
-    for (int j = 0; j < 64; ++j) {
-        float s = b2[j];
-#pragma unroll
-        for (int k = 0; k < 64; ++k) s = fmaf(W2[j * 64 + k], h1[k], s);
-        y = fmaf(W3[j], tanhf(s), y);
-    }
-    return y;
-}
-
 // The group's sum of point p's partials (every lane of the group returns the same bits).
 __device__ __forceinline__ void group_sum(const Geom& G, const double* __restrict__ partial, long long p, int r,
                                           double (&U)[3])
@@ -514,33 +538,29 @@ __device__ __forceinline__ void group_sum(const Geom& G, const double* __restric
         for (int c = 0; c < 3; ++c) U[c] += __shfl_xor(U[c], d, ADV_GP);
 }
 
+__device__ __forceinline__ int point_box(const Geom& G, const AdvectArgs& A, long long i)
+{
+    const int box = A.boxid ? A.boxid[i] : 0;
+    return (box < 0 || box >= G.nboxes) ? 0 : box;
+}
+
 // Outputs and the move of point i (set-local; p = A.off + i) with interpolated velocity U;
-// W: the MLP weights in LDS (used only with A.mlp).
+// y: the network's output for the point (used only with A.mlp).
 __device__ __forceinline__ void finish_point(const Geom& G, const AdvectArgs& A, const BoxDev* __restrict__ boxes,
-                                             long long i, long long p, const double (&U)[3],
-                                             const float* __restrict__ W)
+                                             long long i, long long p, const double (&U)[3], float y)
 {
     for (int c = 0; c < 3; ++c) {
         if (A.vel_out) A.vel_out[3 * i + c] = U[c];
         if (A.vel_sum) A.vel_sum[3 * i + c] += U[c];
     }
     if (!A.advect) return;
-    int box = A.boxid ? A.boxid[i] : 0;
-    if (box < 0 || box >= G.nboxes) box = 0;
+    const int box = point_box(G, A, i);
     const double tau = boxes[box].tau;
     const double eta = G.rho0 * tau / 3.0;
     double inv_aL = A.inv_aL;
-    double R[3] = {A.pos[3 * i], A.pos[3 * i + 1], A.pos[3 * i + 2]};
+    if (A.mlp) inv_aL += double(A.out_scale) * double(y);
+    const double R[3] = {A.pos[3 * i], A.pos[3 * i + 1], A.pos[3 * i + 2]};
     const double L[3] = {double(G.nx), double(G.ny), double(G.nz)};
-    if (A.mlp) {
-        float xin[4];
-        for (int a = 0; a < 3; ++a) {
-            const double r = wrap_pos(R[a], L[a]);
-            xin[a] = (float(r - floor(r)) - A.in_shift[a]) * A.in_scale[a];
-        }
-        xin[3] = (float(tau) - A.in_shift[3]) * A.in_scale[3];
-        inv_aL += double(A.out_scale) * double(mlp_eval(W, xin));
-    }
     const double mob = (A.inv_a - inv_aL) / (6.0 * M_PI * eta);
     double zeta[3] = {0.0, 0.0, 0.0};
     if (A.tin) {
@@ -566,41 +586,76 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
     if (i >= A.n) return;   // whole groups: a group is 8 aligned lanes of one wave
     double U[3];
     group_sum(G, partial, A.off + i, r, U);
-    if (r == 0) finish_point(G, A, boxes, i, A.off + i, U, nullptr);
+    if (r == 0) finish_point(G, A, boxes, i, A.off + i, U, 0.0f);
 }
 
-// With the MLP (a few thousand FLOP per point, which wants every lane busy): the group
-// sums leave U in the point's first partial slot (rewritten by the next step), then one
-// lane per point finishes with the weights staged in LDS.
-__global__ __launch_bounds__(256) void k_advect_sum(const Geom G, long long n, long long off,
-                                                    double* __restrict__ partial)
-{
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long i = gid / ADV_GP;
-    const int r = int(gid % ADV_GP);
-    if (i >= n) return;
-    double U[3];
-    group_sum(G, partial, off + i, r, U);
-    if (r == 0) {
-        double* pp = partial + (off + i) * G.maxp * 3;
-        pp[0] = U[0];
-        pp[1] = U[1];
-        pp[2] = U[2];
-    }
-}
+// With the MLP correction to 1/a_L (4 -> 64 tanh -> 64 tanh -> 1, bf16 weights staged in LDS
+// as FP32, FP32 accumulation): the group of ADV_GP lanes of a point sums its partials as in
+// k_advect, then shares the network: lane r evaluates the hidden units j = r + ADV_GP q
+// (q = 0..7) of both layers, the first layer's outputs go through LDS to the whole group, and
+// a butterfly over the group adds the lanes' parts of the output.  Rows of W2 are padded to
+// 65 floats so that the group's lanes read distinct banks.
+constexpr int MLP_H = 64;
+constexpr int MLP_PAD = MLP_H + 1;
+constexpr int ADV_PTS = 256 / ADV_GP;   // points per block
 
 __global__ __launch_bounds__(256) void k_advect_mlp(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
                                                     const double* __restrict__ partial)
 {
-    __shared__ float W[LBML_NPARAM_DEV];
-    for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) W[k] = bf16_to_f32(A.mlp[k]);
+    __shared__ float W1[MLP_H * 4], b1[MLP_H], W2[MLP_H * MLP_PAD], b2[MLP_H], W3[MLP_H];
+    __shared__ float h1[ADV_PTS][MLP_PAD];
+    __shared__ float b3;
+    // lbml layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
+    for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) {
+        const float v = bf16_to_f32(A.mlp[k]);
+        if (k < 256) W1[k] = v;
+        else if (k < 320) b1[k - 256] = v;
+        else if (k < 4416) W2[((k - 320) >> 6) * MLP_PAD + ((k - 320) & 63)] = v;
+        else if (k < 4480) b2[k - 4416] = v;
+        else if (k < 4544) W3[k - 4480] = v;
+        else b3 = v;
+    }
     __syncthreads();
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i0 = gid / ADV_GP;
+    const int r = int(gid % ADV_GP), pl = threadIdx.x / ADV_GP;
+    const bool live = i0 < A.n;
+    const long long i = live ? i0 : A.n - 1;   // lanes past the end repeat the last point (no writes)
     const long long p = A.off + i;
-    const double* pp = partial + p * G.maxp * 3;
-    const double U[3] = {pp[0], pp[1], pp[2]};
-    finish_point(G, A, boxes, i, p, U, W);
+    double U[3];
+    group_sum(G, partial, p, r, U);
+    // inputs: fractional offsets of the (wrapped) position and the box's tau
+    float xin[4];
+    {
+        const double L[3] = {double(G.nx), double(G.ny), double(G.nz)};
+        for (int a = 0; a < 3; ++a) {
+            const double R = wrap_pos(A.pos[3 * i + a], L[a]);
+            xin[a] = (float(R - floor(R)) - A.in_shift[a]) * A.in_scale[a];
+        }
+        xin[3] = (float(boxes[point_box(G, A, i)].tau) - A.in_shift[3]) * A.in_scale[3];
+    }
+#pragma unroll
+    for (int q = 0; q < MLP_H / ADV_GP; ++q) {
+        const int j = r + ADV_GP * q;
+        float s = b1[j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = fmaf(W1[j * 4 + k], xin[k], s);
+        h1[pl][j] = tanhf(s);
+    }
+    __syncthreads();
+    float y = 0.0f;
+#pragma unroll
+    for (int q = 0; q < MLP_H / ADV_GP; ++q) {
+        const int j = r + ADV_GP * q;
+        float s = b2[j];
+#pragma unroll 16
+        for (int k = 0; k < MLP_H; ++k) s = fmaf(W2[j * MLP_PAD + k], h1[pl][k], s);
+        y = fmaf(W3[j], tanhf(s), y);
+    }
+#pragma unroll
+    for (int d = 1; d < ADV_GP; d <<= 1) y += __shfl_xor(y, d, ADV_GP);
+    y += b3;
+    if (live && r == 0) finish_point(G, A, boxes, i, p, U, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -724,16 +779,18 @@ void launch_fill_u32(void* p, long long n, uint32_t v, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(nblk(n, 256)), dim3(256), 0, s, (uint32_t*)p, n, v);
 }
 
+long long prep_blocks(long long n) { return n > 0 ? nblk(n, 256) : 0; }
+
 void launch_prep(int storage, const Geom& G, long long n, long long off, const double* pos, const double* frc,
-                 const int* boxid, void* rec, int* err, hipStream_t s)
+                 const int* boxid, void* rec, int* err, double* psum, hipStream_t s)
 {
     if (n <= 0) return;
     if (storage == ST_FP64)
         hipLaunchKernelGGL(k_prep<double>, dim3(nblk(n, 256)), dim3(256), 0, s, G, n, off, pos, frc, boxid,
-                           (PRec<double>*)rec, err);
+                           (PRec<double>*)rec, err, psum);
     else
         hipLaunchKernelGGL(k_prep<float>, dim3(nblk(n, 256)), dim3(256), 0, s, G, n, off, pos, frc, boxid,
-                           (PRec<float>*)rec, err);
+                           (PRec<float>*)rec, err, psum);
 }
 
 long long scan_blocks(long long ntiles) { return (ntiles + SCAN_B - 1) / SCAN_B; }
@@ -744,43 +801,42 @@ void launch_bins(int storage, const Geom& G, long long npts, const void* rec, in
                  int* cursor, int* tlist, int* tlist_tmp, hipStream_t s)
 {
     const int gp = lanes_per_point(G.maxp);
+    const unsigned gb = std::min<unsigned>(BIN_GRID, nblk(std::max(npts * gp, 1LL), 256));
     if (npts > 0) {
         if (storage == ST_FP64)
-            hipLaunchKernelGGL(k_count<double>, dim3(nblk(npts * gp, 256)), dim3(256), 0, s, G, npts, 0LL, gp,
-                               (const PRec<double>*)rec, count);
+            hipLaunchKernelGGL(k_count<double>, dim3(gb), dim3(256), 0, s, G, npts, gp, (const PRec<double>*)rec,
+                               count);
         else
-            hipLaunchKernelGGL(k_count<float>, dim3(nblk(npts * gp, 256)), dim3(256), 0, s, G, npts, 0LL, gp,
-                               (const PRec<float>*)rec, count);
+            hipLaunchKernelGGL(k_count<float>, dim3(gb), dim3(256), 0, s, G, npts, gp, (const PRec<float>*)rec,
+                               count);
     }
-    const unsigned nb = (unsigned)scan_blocks(G.ntiles);
+    const unsigned nb = (unsigned)std::min<long long>(SCAN_GRID, scan_blocks(G.ntiles));
     hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, (const int*)count, bsum,
                        (const int*)G.rebin);
     hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, count, (const int*)bsum, toff, cursor,
                        (const int*)G.rebin);
     if (npts <= 0) return;
     const long long max_entries = npts * G.maxp;
-    hipLaunchKernelGGL(k_fill, dim3(nblk(npts * gp, 256)), dim3(256), 0, s, G, npts, gp, (const int*)toff, cursor,
-                       tlist_tmp);
-    hipLaunchKernelGGL(k_sort_slots, dim3(nblk(max_entries, 256)), dim3(256), 0, s, G, max_entries, (const int*)toff,
-                       (const int*)tlist_tmp, tlist);
+    hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, s, G, npts, gp, (const int*)toff, cursor, tlist_tmp);
+    hipLaunchKernelGGL(k_sort_slots, dim3(std::min<unsigned>(BIN_GRID, nblk(max_entries, 256))), dim3(256), 0, s, G,
+                       max_entries, (const int*)toff, (const int*)tlist_tmp, tlist);
 }
 
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
-                       const float* tmax, double* part, float* pmax, unsigned* ticket, BoxDev* boxes, int zero_net,
-                       int fp16_exp, hipStream_t s)
+                       const double* psum, long long npsum, const float* tmax, double* part, float* pmax,
+                       unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s)
 {
     const dim3 grid(G.nboxes, G.bchunks);
     if (storage == ST_FP64)
-        hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, tmax,
-                           part, pmax, ticket, boxes, zero_net, fp16_exp);
+        hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, psum,
+                           npsum, tmax, part, pmax, ticket, boxes, zero_net, fp16_exp);
     else
-        hipLaunchKernelGGL(k_box_update<float>, grid, dim3(256), 0, s, G, (const PRec<float>*)rec, toff, tlist, tmax,
-                           part, pmax, ticket, boxes, zero_net, fp16_exp);
+        hipLaunchKernelGGL(k_box_update<float>, grid, dim3(256), 0, s, G, (const PRec<float>*)rec, toff, tlist, psum,
+                           npsum, tmax, part, pmax, ticket, boxes, zero_net, fp16_exp);
 }
 
 
-void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial,
-                   hipStream_t s)
+void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial, hipStream_t s)
 {
     if (a.n <= 0) return;
     AdvectArgs A;
@@ -801,12 +857,11 @@ void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, do
     A.out_scale = a.out_scale;
     A.advect = a.advect;
     A.tin = a.tin;
-    if (A.mlp) {
-        hipLaunchKernelGGL(k_advect_sum, dim3(nblk(a.n * ADV_GP, 256)), dim3(256), 0, s, G, a.n, a.off, partial);
-        hipLaunchKernelGGL(k_advect_mlp, dim3(nblk(a.n, 256)), dim3(256), 0, s, G, A, boxes, (const double*)partial);
-    } else {
-        hipLaunchKernelGGL(k_advect, dim3(nblk(a.n * ADV_GP, 256)), dim3(256), 0, s, G, A, boxes, (const double*)partial);
-    }
+    const unsigned nb = nblk(a.n * ADV_GP, 256);
+    if (A.mlp)
+        hipLaunchKernelGGL(k_advect_mlp, dim3(nb), dim3(256), 0, s, G, A, boxes, (const double*)partial);
+    else
+        hipLaunchKernelGGL(k_advect, dim3(nb), dim3(256), 0, s, G, A, boxes, (const double*)partial);
 }
 
 void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,

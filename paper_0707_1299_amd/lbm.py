@@ -24,6 +24,7 @@ LB_ERR_HIP = -3
 LB_ERR_NONFINITE = -4
 LB_ERR_CAPACITY = -5
 LB_ERR_STATE = -6
+LB_ERR_NEGATIVE_DENSITY = -7
 
 LB_STORAGE_FP64 = 0
 LB_STORAGE_FP32 = 1
@@ -39,7 +40,7 @@ LB_FORCES_NEXT_STEP = 0
 LB_FORCES_STATIC = 1
 LB_COLLOIDS = 2
 
-LB_NDIAG = 12
+LB_NDIAG = 13
 LBML_NPARAM = 4545
 
 STORAGE = {"fp64": LB_STORAGE_FP64, "fp32": LB_STORAGE_FP32, "fp16": LB_STORAGE_FP16, "mom32": LB_STORAGE_MOM32}
@@ -121,6 +122,9 @@ def _load():
         "lb_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lb_last_error": (ctypes.c_char_p, [vp]),
         "lb_steps_taken": (i64, [vp]),
+        "lb_checkpoint_bytes": (ctypes.c_int, [vp, P(ctypes.c_size_t)]),
+        "lb_checkpoint_save": (ctypes.c_int, [vp, vp]),
+        "lb_checkpoint_load": (ctypes.c_int, [vp, vp]),
         "lb_kernel_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "lb_kernel_time": (ctypes.c_int, [vp, P(dbl), P(i64)]),
         "lb_copy_probe": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
@@ -353,6 +357,22 @@ class Lattice:
 
     def steps_taken(self):
         return int(_L.lb_steps_taken(self.ctx))
+
+    def checkpoint_bytes(self):
+        n = ctypes.c_size_t(0)
+        self._check(_L.lb_checkpoint_bytes(self.ctx, ctypes.byref(n)))
+        return n.value
+
+    def checkpoint_save(self, buf):
+        """Copy the state into buf (a device uint8 tensor of at least checkpoint_bytes() + 256 bytes);
+        returns the 256-byte aligned address used."""
+        p = buf.data_ptr() + ((-buf.data_ptr()) % 256)
+        self._check(_L.lb_checkpoint_save(self.ctx, ctypes.c_void_p(p)))
+        return p
+
+    def checkpoint_load(self, buf):
+        p = buf.data_ptr() + ((-buf.data_ptr()) % 256)
+        self._check(_L.lb_checkpoint_load(self.ctx, ctypes.c_void_p(p)))
 
     def kernel_timing(self, enable=True):
         self._check(_L.lb_kernel_timing(self.ctx, int(bool(enable))))

@@ -85,7 +85,7 @@ def test_point_capacity_limits():
 
 def test_status_strings():
     for code in (lbm.LB_OK, lbm.LB_ERR_ARG, lbm.LB_ERR_SIZE, lbm.LB_ERR_HIP, lbm.LB_ERR_NONFINITE,
-                 lbm.LB_ERR_CAPACITY, lbm.LB_ERR_STATE):
+                 lbm.LB_ERR_CAPACITY, lbm.LB_ERR_STATE, lbm.LB_ERR_NEGATIVE_DENSITY):
         s = lbm.lb_status_string(code)
         assert s and s != "unknown status"
     assert lbm.lb_status_string(12345) == "unknown status"

@@ -95,7 +95,7 @@ def test_sedimenting_chains_match_oracle(storage):
     print("chains %s: u rel %.3e, pos err %.3e (disp %.3e)" % (storage, e, d, disp))
     assert e <= TOL[storage]
     assert d <= TOL[storage] * disp
-    assert rel(out["chain"][1], box.sets[0]["U"]) <= 10 * TOL[storage]
+    assert rel(out["chain"][1], box.sets[0]["U"]) <= TOL[storage]
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])

@@ -76,7 +76,7 @@ def test_stokeslet_32cubed_500_steps(storage):
     assert e <= TOL[storage]
     # interpolated velocity at the force, last step
     U = outs[0][1].cpu().numpy()
-    assert rel(U, box.sets[0].U) <= TOL[storage] * 10
+    assert rel(U, box.sets[0].U) <= TOL[storage]
 
 
 @pytest.mark.parametrize("storage,tile,variant", [
@@ -101,7 +101,7 @@ def test_ragged_multi_tile_forces_zero_net(storage, tile, variant):
     e = rel(u[0], uo)
     print("ragged %s %s v%d rel err %.3e" % (storage, tile, variant, e))
     assert e <= TOL[storage]
-    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
+    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage]
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "mom32"])
@@ -137,7 +137,7 @@ def test_colloids_advected(storage):
     print("colloids %s u rel %.3e pos err %.3e (disp %.3e)" % (storage, e, dR.max(), disp))
     assert e <= TOL[storage]
     assert dR.max() <= TOL[storage] * disp
-    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage] * 10
+    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL[storage]
 
 
 @pytest.mark.parametrize("storage,tile", [("fp64", (16, 4, 4)), ("fp32", (256, 1, 1)), ("fp32", (32, 2, 4)),
@@ -160,9 +160,13 @@ def test_colloids_cross_binning_windows(storage, tile):
     lat.add_point_forces(p, dev(frc), None, lbm.LB_COLLOIDS, lbm.PointModel(vel_out=vel, **model))
     box = oracle.Box(shape, 0.7, 1.0, zero_net_force=True)
     box.sets = [oracle.ForceSet(pos.copy(), frc.copy(), kind="colloid", inv_a=model["inv_a"], inv_aL=model["inv_aL"])]
+    moved = 0.0      # displacement by the dynamics so far (the shifts by hand are exact)
     for sh in ((0.7, -1.3, 2.2), (-2.6, 0.4, -0.9), (1.1, 1.6, -1.7), (0.0, 0.0, 0.0)):
+        before = box.sets[0].pos.copy()
         lat.step(30)
         box.step(30)
+        d = np.abs(box.sets[0].pos - before)
+        moved += np.minimum(d, L - d).max()
         _, u = lat.moments(rho=False)
         lat.sync()
         _, uo = box.moments()
@@ -170,10 +174,11 @@ def test_colloids_cross_binning_windows(storage, tile):
         R = p.cpu().numpy()
         dR = np.abs(R - box.sets[0].pos)
         dR = np.minimum(dR, L - dR).max()
-        print("cross %s %s u rel %.3e pos err %.3e" % (storage, tile, e, dR))
+        eU = rel(vel.cpu().numpy(), box.sets[0].U)
+        print("cross %s %s u rel %.3e U rel %.3e pos err %.3e (moved %.3e)" % (storage, tile, e, eU, dR, moved))
         assert e <= tol
-        assert dR <= tol * 10
-        assert rel(vel.cpu().numpy(), box.sets[0].U) <= tol * 10
+        assert dR <= tol * moved
+        assert eU <= tol
         # move every colloid by more than the window's margin, on both sides
         box.sets[0].pos = np.mod(box.sets[0].pos + np.array(sh), L)
         p.copy_(dev(np.mod(R + np.array(sh), L)))
@@ -221,7 +226,7 @@ def test_interp_velocity_at_arbitrary_points(storage):
     q = np.random.default_rng(9).uniform(-5, 25, size=(50, 3))
     Ug = lat.interp_velocity(dev(q)).cpu().numpy()
     Uo = box.interp_velocity(q)
-    assert rel(Ug, Uo) <= TOL[storage] * 10
+    assert rel(Ug, Uo) <= TOL[storage]
 
 
 def test_diagnostics_mass_momentum_force_moments():
@@ -326,6 +331,22 @@ def test_graph_replay_equals_eager_and_is_deterministic():
     assert np.array_equal(o1[0][0].cpu().numpy(), o2[0][0].cpu().numpy())
 
 
+def test_negative_density_flagged():
+    """A state with non-positive density at some nodes (an equilibrium set there with rho <= 0)
+    is counted per box and reported by lb_diagnostics."""
+    shape = (8, 10, 12)
+    rho = np.ones((2,) + shape)
+    rho[1, 3, 4, 5] = -0.25
+    rho[1, 6, 2, 9] = 0.0
+    u = np.zeros((2, 3) + shape)
+    lat = lbm.Lattice(shape, "fp64", nboxes=2, tau=0.8)
+    lat.set_equilibrium(dev(rho), dev(u))
+    r, d = lat.diagnostics()
+    assert r == lbm.LB_ERR_NEGATIVE_DENSITY
+    assert d[0, 12] == 0 and d[1, 12] == 2 and d[1, 11] == 0
+    assert abs(d[1, 0] - (rho[1] - 1).sum()) < 1e-12
+
+
 def test_next_step_forces_apply_once():
     shape = (12, 12, 12)
     pos = np.array([[5.3, 6.1, 4.7]])
@@ -378,7 +399,7 @@ def test_full_size_128_fp32_bench_configuration():
     e = rel(u[0], uo)
     print("128^3 fp32 rel err %.3e" % e)
     assert e <= TOL["fp32"]
-    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= 1e-4
+    assert rel(outs[0][1].cpu().numpy(), box.sets[0].U) <= TOL["fp32"]
 
 
 # ---- FP16-scaled storage: error against the FP64 oracle, stated per output ----

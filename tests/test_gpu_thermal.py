@@ -85,7 +85,7 @@ def test_thermal_step_matches_oracle(storage, op):
     e, eU = rel(u, uo), rel(outs[0][1], box.sets[0]["U"])
     print("thermal %s %s: u rel %.3e, U rel %.3e (|u| %.2e)" % (op, storage, e, eU, np.abs(uo).max()))
     assert e <= TOL[storage]
-    assert eU <= 10 * TOL[storage]
+    assert eU <= TOL[storage]
 
 
 def test_brownian_colloids_match_oracle():
