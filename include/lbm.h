@@ -380,6 +380,22 @@ int lbml_loss_grad(const uint16_t* d_w16, int64_t n, const float* d_x, const flo
 int lbml_adam_step(float* d_master, float* d_m, float* d_v, const float* d_grad, uint16_t* d_w16, int32_t t,
                    float lr, float beta1, float beta2, float eps, void* hip_stream);
 
+/*
+ * lbml_loss_grad without a work argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid allocation): the per-sample work lives in a
+ * device array inside the library, sized for n <= LBML_STATIC_MAX_N samples
+ * (4.2 MB, held on each device the library runs on until the process ends).
+ * Same results as lbml_loss_grad, bit for bit.  The call allocates nothing;
+ * its first call on a device looks up that device's copy of the array.
+ * Errors: LB_ERR_ARG (n <= 0, NULL pointers), LB_ERR_SIZE (n above
+ * LBML_STATIC_MAX_N), LB_ERR_HIP.  Every call on one device uses the same
+ * array: calls that may overlap on one device (other streams, other threads)
+ * race and must be ordered by the caller.
+ */
+#define LBML_STATIC_MAX_N 4096
+int lbml_loss_grad_static(const uint16_t* d_w16, int64_t n, const float* d_x, const float* d_target, float* d_grad,
+                          float* d_loss, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,8 @@
 // calls give bit-identical gradients.
 #include <math.h>
 
+#include <mutex>
+
 #include "../../include/lbm.h"
 #include "lbm_device.h"
 
@@ -180,6 +182,46 @@ __global__ void k_adam(float* __restrict__ m0, float* __restrict__ m1, float* __
     w16[i] = f2bf16(w);
 }
 
+// the two passes of the gradient: per-sample quantities into work, then the per-parameter sums
+void launch_loss_grad(const uint16_t* d_w16, long long n, const float* d_x, const float* d_target, float* d_grad,
+                      float* d_loss, float* d_work, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_backprop, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_w16, n, d_x, d_target,
+                       d_work);
+    hipLaunchKernelGGL(k_grad, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, n, d_x, (const float*)d_work, d_grad,
+                       d_loss);
+}
+
+}  // namespace
+
+// Work memory of lbml_loss_grad_static: a device array in the library itself, sized for
+// LBML_STATIC_MAX_N samples (lbml_work_floats of that many).  Its name is a host-side stand-in:
+// kernels receive the device address that hipGetSymbolAddress returns, taken once per device
+// (with that device current) and kept in scratch_dev.  Every call on one device shares the array;
+// the gradient pass writes every value it reads, so nothing needs clearing between calls.
+static __device__ __align__(256) float scratch[258LL * LBML_STATIC_MAX_N];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float* scratch_dev[MAX_DEVICES] = {};
+
+int scratch_ptr(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return LB_ERR_HIP;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return LB_ERR_HIP;
+        scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = scratch_dev[dev];
+    return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -206,11 +248,21 @@ int lbml_loss_grad(const uint16_t* d_w16, int64_t n, const float* d_x, const flo
                    float* d_loss, float* d_work, void* hip_stream)
 {
     if (n <= 0 || !d_w16 || !d_x || !d_target || !d_grad || !d_loss || !d_work) return LB_ERR_ARG;
-    hipStream_t s = (hipStream_t)hip_stream;
-    hipLaunchKernelGGL(k_backprop, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_w16, (long long)n, d_x,
-                       d_target, d_work);
-    hipLaunchKernelGGL(k_grad, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, (long long)n, d_x, (const float*)d_work,
-                       d_grad, d_loss);
+    (void)hipGetLastError();
+    launch_loss_grad(d_w16, (long long)n, d_x, d_target, d_grad, d_loss, d_work, (hipStream_t)hip_stream);
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_ERR_HIP;
+}
+
+int lbml_loss_grad_static(const uint16_t* d_w16, int64_t n, const float* d_x, const float* d_target, float* d_grad,
+                          float* d_loss, void* hip_stream)
+{
+    if (n <= 0 || !d_w16 || !d_x || !d_target || !d_grad || !d_loss) return LB_ERR_ARG;
+    if (n > LBML_STATIC_MAX_N) return LB_ERR_SIZE;
+    float* work = nullptr;
+    const int r = scratch_ptr(&work);
+    if (r) return r;
+    (void)hipGetLastError();
+    launch_loss_grad(d_w16, (long long)n, d_x, d_target, d_grad, d_loss, work, (hipStream_t)hip_stream);
     return hipGetLastError() == hipSuccess ? LB_OK : LB_ERR_HIP;
 }
 

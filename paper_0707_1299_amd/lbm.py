@@ -133,6 +133,7 @@ def _load():
         "lbml_round_bf16": (ctypes.c_int, [vp, vp, vp]),
         "lbml_forward": (ctypes.c_int, [vp, i64, vp, vp, vp]),
         "lbml_loss_grad": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp]),
+        "lbml_loss_grad_static": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp]),
         "lbml_adam_step": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_float, vp]),
     }
@@ -405,6 +406,17 @@ def lbml_forward(w16, x, y):
 def lbml_loss_grad(w16, x, target, grad, loss, work):
     r = _L.lbml_loss_grad(_ptr(w16), x.shape[0], _ptr(x), _ptr(target), _ptr(grad), _ptr(loss), _ptr(work),
                           _stream_handle())
+    if r != LB_OK:
+        raise LBError(r)
+
+
+LBML_STATIC_MAX_N = 4096
+
+
+def lbml_loss_grad_static(w16, x, target, grad, loss):
+    """lbml_loss_grad with the library's own work array (no work argument; n <= LBML_STATIC_MAX_N)."""
+    r = _L.lbml_loss_grad_static(_ptr(w16), x.shape[0], _ptr(x), _ptr(target), _ptr(grad), _ptr(loss),
+                                 _stream_handle())
     if r != LB_OK:
         raise LBError(r)
 

@@ -102,6 +102,7 @@ static void entry_argument_checks()
     CHECK(lbml_forward(nullptr, 4, nullptr, nullptr, nullptr) == LB_ERR_ARG);
     CHECK(lbml_forward(nullptr, 0, nullptr, nullptr, nullptr) == LB_OK);
     CHECK(lbml_loss_grad(nullptr, 4, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == LB_ERR_ARG);
+    CHECK(lbml_loss_grad_static(nullptr, 4, nullptr, nullptr, nullptr, nullptr, nullptr) == LB_ERR_ARG);
     CHECK(lbml_adam_step(nullptr, nullptr, nullptr, nullptr, nullptr, 1, 1e-3f, 0.9f, 0.999f, 1e-8f, nullptr) ==
           LB_ERR_ARG);
     for (int s = -9; s <= 1; ++s) CHECK(strlen(lb_status_string(s)) > 0);

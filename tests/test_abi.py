@@ -26,7 +26,7 @@ def test_header_declares_the_documented_calls():
     names = declared_functions()
     for required in ("lb_init", "lb_add_point_forces", "lb_step", "lb_moments", "lb_interp_velocity",
                      "lb_workspace_bytes", "lb_diagnostics", "lb_sync", "lb_destroy", "lb_status_string",
-                     "lb_last_error", "lbml_forward", "lbml_loss_grad", "lbml_adam_step"):
+                     "lb_last_error", "lbml_forward", "lbml_loss_grad", "lbml_adam_step", "lbml_loss_grad_static"):
         assert required in names
 
 
