@@ -49,7 +49,7 @@ int max_axis_tiles(int n, int t)
 }
 
 struct Layout {
-    size_t pop[2], boxes, rec, psum, count, cursor, toff, bsum, tlist, tlist_tmp, partial, fpart, pmax, tmax, ticket,
+    size_t pop[2], boxes, rec, psum, count, cursor, toff, bsum, tlist, tlist_tmp, partial, fpart, pmax, tmax, smax, ticket,
         tctr,
         err, nf, rebin, rebox, win,
         diag, diagout;
@@ -119,6 +119,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     memset(&G, 0, sizeof(G));
     G.nx = p->nx; G.ny = p->ny; G.nz = p->nz; G.nboxes = p->nboxes;
     G.tx = tx; G.ty = ty; G.tz = tz;
+    G.ltx = __builtin_ctz(tx); G.lty = __builtin_ctz(ty); G.ltz = __builtin_ctz(tz);
     G.ntx = (p->nx + tx - 1) / tx;
     G.nty = (p->ny + ty - 1) / ty;
     G.ntz = (p->nz + tz - 1) / tz;
@@ -176,6 +177,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     L.fpart = take(sizeof(double) * 3 * p->nboxes * P.chunks);
     L.pmax = take(sizeof(float) * p->nboxes * P.chunks);
     L.tmax = take(sizeof(float) * G.ntiles);
+    L.smax = take(sizeof(unsigned) * SMAX_SLOTS * SMAX_STRIDE);
     L.ticket = take(sizeof(unsigned) * p->nboxes);
     L.tctr = take(2 * sizeof(unsigned long long));
     L.err = take(sizeof(int) * 4);
@@ -212,7 +214,7 @@ struct CkptHeader {
     char magic[8];
     int32_t nx, ny, nz, nboxes, storage, collision, tx, ty, tz, pad;
     int64_t steps, npoints, pop_bytes, tiles, total;
-    int64_t off_pop, off_boxes, off_tmax, off_tctr, off_nf, off_win;
+    int64_t off_pop, off_boxes, off_tmax, off_smax, off_tctr, off_nf, off_win;
 };
 constexpr char CKPT_MAGIC[8] = {'l', 'b', 'c', 'k', 'p', 't', '0', '1'};
 
@@ -264,6 +266,7 @@ struct lb_ctx {
     double* fpart() const { return (double*)(ws + P.L.fpart); }
     float* pmax() const { return (float*)(ws + P.L.pmax); }
     float* tmax() const { return (float*)(ws + P.L.tmax); }
+    unsigned* smax() const { return (unsigned*)(ws + P.L.smax); }
     unsigned* ticket() const { return (unsigned*)(ws + P.L.ticket); }
     unsigned long long* tctr() const { return (unsigned long long*)(ws + P.L.tctr); }
     int* errw() const { return (int*)(ws + P.L.err); }
@@ -439,7 +442,7 @@ void enqueue_step(lb_ctx* c, hipStream_t s, bool rebuild)
                 }
                 a.out_scale = st.model.out_scale;
             }
-            launch_advect(G, a, c->boxes(), c->partial(), s);
+            launch_advect(c->p.storage, G, a, c->boxes(), c->partial(), s);
         }
         off += st.n;
     }
@@ -537,6 +540,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     c->P.G.rebin = c->rebin();
     c->P.G.rebox = c->rebox();
     c->P.G.win = c->win();
+    c->P.G.smax = (p->storage == LB_STORAGE_FP16 && p->nboxes == 1) ? c->smax() : nullptr;
     c->stream = (hipStream_t)hip_stream;
     c->cap_stream = nullptr;
     c->cur = 0;
@@ -578,6 +582,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
         B.nz_g = sqrt(mu * (1.0 - gg * gg));
         const double eta = P.G.rho0 * p->tau[b] / 3.0;
         B.pn = p->kT / (3.0 * M_PI * eta);
+        B.inv6pe = 1.0 / (6.0 * M_PI * eta);
         B.e_data = e0;
         B.s_in = ldexpf(1.0f, -e0);
         B.s_out = ldexpf(1.0f, e0);
@@ -593,6 +598,7 @@ int lb_init(const lb_params* p, void* d_workspace, size_t bytes, void* hip_strea
     launch_fill_u32(c->ticket(), p->nboxes, 0u, s);
     launch_fill_u32(c->tctr(), 4, 0u, s);
     launch_fill_u32(c->tmax(), G.ntiles, 0u, s);
+    launch_fill_u32(c->smax(), SMAX_SLOTS * SMAX_STRIDE, 0u, s);
     launch_fill_u32(c->errw(), 4, 0u, s);
     launch_fill_u32(c->nf(), p->nboxes, 0u, s);
     launch_fill_u32(c->rebin(), 1, 1u, s);
@@ -872,6 +878,7 @@ static CkptHeader ckpt_layout(const lb_ctx* c)
     h.off_pop = take(h.pop_bytes);
     h.off_boxes = take(sizeof(BoxDev) * G.nboxes);
     h.off_tmax = take(sizeof(float) * G.ntiles);
+    h.off_smax = take(sizeof(unsigned) * SMAX_SLOTS * SMAX_STRIDE);
     h.off_tctr = take(sizeof(unsigned long long));
     h.off_nf = take(sizeof(int) * G.nboxes);
     h.off_win = take(sizeof(int4) * std::max<long long>(h.npoints, 1));
@@ -906,6 +913,7 @@ int lb_checkpoint_save(lb_ctx* c, void* dst)
     cp(h.off_pop, c->pop(c->cur), (size_t)h.pop_bytes);
     cp(h.off_boxes, c->boxes(), sizeof(BoxDev) * c->p.nboxes);
     cp(h.off_tmax, c->tmax(), sizeof(float) * c->P.G.ntiles);
+    cp(h.off_smax, c->smax(), sizeof(unsigned) * SMAX_SLOTS * SMAX_STRIDE);
     cp(h.off_tctr, c->tctr() + c->cur, sizeof(unsigned long long));
     cp(h.off_nf, c->nf(), sizeof(int) * c->p.nboxes);
     if (h.npoints > 0) cp(h.off_win, c->win(), sizeof(int4) * h.npoints);
@@ -935,6 +943,7 @@ int lb_checkpoint_load(lb_ctx* c, const void* src)
     cp(c->pop(c->cur), h.off_pop, (size_t)h.pop_bytes);
     cp(c->boxes(), h.off_boxes, sizeof(BoxDev) * c->p.nboxes);
     cp(c->tmax(), h.off_tmax, sizeof(float) * c->P.G.ntiles);
+    cp(c->smax(), h.off_smax, sizeof(unsigned) * SMAX_SLOTS * SMAX_STRIDE);
     cp(c->tctr() + c->cur, h.off_tctr, sizeof(unsigned long long));
     cp(c->nf(), h.off_nf, sizeof(int) * c->p.nboxes);
     if (h.npoints > 0) cp(c->win(), h.off_win, sizeof(int4) * h.npoints);

@@ -71,6 +71,10 @@ template <class T> struct alignas(16) PRec {
     T pad;
 };
 
+// FP16 maxima of a one-box lattice: slots and their spacing (one 128-byte line each)
+constexpr int SMAX_SLOTS = 256;
+constexpr int SMAX_STRIDE = 32;
+
 // Per-box parameters read by the step kernels.
 struct alignas(16) BoxDev {
     double tau;
@@ -83,6 +87,7 @@ struct alignas(16) BoxDev {
     double nz_s;       // ... of the shear modes
     double nz_g;       // ... of the ghost modes
     double pn;         // particle noise: variance kT / (3 pi eta) per unit of 1/a - 1/a_L
+    double inv6pe;     // 1 / (6 pi eta), eta = rho0 tau / 3: the Stokes mobility of the colloid update
     float s_in;        // FP16: dequantise multiplier 2^-e of the stored data
     float s_out;       // FP16: quantise multiplier 2^e of the data written this step
     int e_data;        // FP16: exponent of the data currently stored
@@ -92,7 +97,8 @@ struct alignas(16) BoxDev {
 // Geometry of the lattice and its tiles (all boxes share it).
 struct Geom {
     int nx, ny, nz, nboxes;
-    int tx, ty, tz;       // tile extent per axis (tx * ty * tz == BLOCK)
+    int tx, ty, tz;       // tile extent per axis (tx * ty * tz == BLOCK), powers of two
+    int ltx, lty, ltz;    // their base-2 logarithms
     int ntx, nty, ntz;    // tiles per axis
     int maxp;             // most tiles met by one point's binning window (5 nodes per axis)
     int bchunks;          // blocks per box of the per-box force / maximum reductions
@@ -103,6 +109,9 @@ struct Geom {
     int* rebin;           // set when a point's stencil has left its binning window (tile lists stale)
     int* rebox;           // per box: a point of the box left its window (its windows are chosen again)
     int4* win;            // per point: window base (x, y, z) and box the tile lists were built with
+    unsigned* smax;       // FP16, one box: the box's largest bracket as float bits, spread over
+                          // SMAX_SLOTS slots a cache line apart (tile t updates slot t % SMAX_SLOTS);
+                          // NULL: per-tile maxima instead
     int coll;             // 1: general collision (bulk rate, ghost moments kept); 2: with thermal noise
     unsigned seed_lo, seed_hi;   // key of the noise generator
     long long N;          // nodes per box
@@ -272,6 +281,13 @@ __host__ __device__ __forceinline__ long long pop_index(long long rb, long long 
 // The descriptors' record counts bound every access to its row block or box.
 enum Addr { A_ROW = 0, A_BOX32 = 1, A_G64 = 2 };
 
+// A_ROW: start of row block `row` (32-bit row-block size: 19 planes of a row are far below 4 GiB)
+template <class S>
+__device__ __forceinline__ const char* row_block(const S* base, long long rb, unsigned row)
+{
+    return reinterpret_cast<const char*>(base) + (unsigned long long)row * (unsigned(rb) * unsigned(sizeof(S)));
+}
+
 template <class S, bool NTL, int ADDR>
 __device__ __forceinline__ S load_pop(const S* __restrict__ sb, long long rb, long long kp, unsigned box_bytes, int k,
                                       unsigned row, int x)
@@ -280,7 +296,7 @@ __device__ __forceinline__ S load_pop(const S* __restrict__ sb, long long rb, lo
     constexpr unsigned E = sizeof(S);
     if constexpr (ADDR == A_ROW) {
         const unsigned srow = __builtin_amdgcn_readfirstlane(row);
-        return bload<S, AUX>(plane_rsrc(sb + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * E), unsigned(x) * E,
+        return bload<S, AUX>(plane_rsrc(row_block(sb, rb, srow), unsigned(rb) * E), unsigned(x) * E,
                              unsigned(k) * unsigned(kp) * E);
     } else if constexpr (ADDR == A_BOX32) {
         return bload<S, AUX>(plane_rsrc(sb, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * E,
@@ -302,7 +318,7 @@ __device__ __forceinline__ void store_pop(S v, S* __restrict__ db, long long rb,
     constexpr unsigned E = sizeof(S);
     if constexpr (ADDR == A_ROW) {
         const unsigned srow = __builtin_amdgcn_readfirstlane(row);
-        bstore<S, 2>(v, plane_rsrc(db + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * E), unsigned(x) * E,
+        bstore<S, 2>(v, plane_rsrc(row_block(db, rb, srow), unsigned(rb) * E), unsigned(x) * E,
                      unsigned(k) * unsigned(kp) * E);
     } else if constexpr (ADDR == A_BOX32) {
         bstore<S, 2>(v, plane_rsrc(db, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * E,
@@ -322,7 +338,7 @@ __device__ __forceinline__ uint32_t load_pair(const _Float16* __restrict__ sb, l
     constexpr int AUX = NTL ? 2 : 0;
     if constexpr (ADDR == A_ROW) {
         const unsigned srow = __builtin_amdgcn_readfirstlane(row);
-        return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(sb + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * 2u),
+        return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(row_block(sb, rb, srow), unsigned(rb) * 2u),
                                                     unsigned(x) * 2u, unsigned(k) * unsigned(kp) * 2u, AUX);
     } else if constexpr (ADDR == A_BOX32) {
         return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(sb, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * 2u,
@@ -342,7 +358,7 @@ __device__ __forceinline__ void store_pair(uint32_t v, _Float16* __restrict__ db
 {
     if constexpr (ADDR == A_ROW) {
         const unsigned srow = __builtin_amdgcn_readfirstlane(row);
-        __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(db + pop_index(rb, kp, 0, srow, 0), unsigned(rb) * 2u),
+        __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(row_block(db, rb, srow), unsigned(rb) * 2u),
                                               unsigned(x) * 2u, unsigned(k) * unsigned(kp) * 2u, 2);
     } else if constexpr (ADDR == A_BOX32) {
         __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(db, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * 2u,
@@ -453,6 +469,7 @@ __device__ __forceinline__ void pull_node(const typename StoreT<ST>::S* __restri
 // Wrap r into [0, L).
 __device__ __forceinline__ double wrap_pos(double r, double L)
 {
+    if (r >= 0.0 && r < L) return r + 0.0;   // the usual case (+ 0.0: a negative zero becomes +0)
     r -= L * floor(r / L);
     if (r >= L) r -= L;
     if (r < 0.0) r = 0.0;

@@ -58,7 +58,8 @@ void launch_bins(int storage, const Geom& G, long long npts, const void* rec, in
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
                        const double* psum, long long npsum, const float* tmax, double* part, float* pmax,
                        unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s);
-void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial, hipStream_t s);
+void launch_advect(int storage, const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, void* partial,
+                   hipStream_t s);
 void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,
                           const void* src, const BoxDev* boxes, const int* toff, const int* tlist, const void* rec,
                           hipStream_t s);

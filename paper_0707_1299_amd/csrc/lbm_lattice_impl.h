@@ -59,13 +59,15 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     constexpr int LX = TX / NPL;              // lanes along x in a tile row
     constexpr int NW = BLOCK / NPL / 64;      // waves per block
 
-    int t = tile;
-    const int itx = t % G.ntx;
-    t /= G.ntx;
-    const int ity = t % G.nty;
-    t /= G.nty;
-    const int itz = t % G.ntz;
-    const int box = t / G.ntz;
+    // (unsigned: divisions by the tile counts are then a multiply-high and a shift in the
+    // scalar unit, with no sign corrections)
+    unsigned t = unsigned(tile);
+    const int itx = int(t % unsigned(G.ntx));
+    t /= unsigned(G.ntx);
+    const int ity = int(t % unsigned(G.nty));
+    t /= unsigned(G.nty);
+    const int itz = int(t % unsigned(G.ntz));
+    const int box = int(t / unsigned(G.ntz));
     // a tile row of at least 64 lanes puts each wave on one row: y and z are then wave-uniform
     // and live in scalar registers (so do the upstream row indices of the pull)
     const int tid_w = LX >= 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x)) : int(threadIdx.x);
@@ -424,8 +426,13 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             float t = wm[0];
 #pragma unroll
             for (int q = 1; q < NW; ++q) t = fmaxf(t, wm[q]);
-            // the largest |f*_i / w_i| of the tile, without the scale (1 / 2^e is exact)
-            ((float*)out1)[tile] = FOLD ? t * (1.0f / B.s_out) : t;
+            // the largest |f*_i / w_i| of the tile, without the scale (1 / 2^e is exact); one box:
+            // into the box's maximum (non-negative floats order as their bit patterns)
+            t = FOLD ? t * (1.0f / B.s_out) : t;
+            if (G.smax)
+                atomicMax(G.smax + (tile % SMAX_SLOTS) * SMAX_STRIDE, __float_as_uint(t));
+            else
+                ((float*)out1)[tile] = t;
         }
         __syncthreads();   // wm is rewritten by the block's next tile
     }
@@ -457,10 +464,12 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             if (gz >= G.nz) gz -= G.nz;
             const int lx2 = gx - x0, ly2 = gy - y0, lz2 = gz - z0;
             const bool in = unsigned(lx2) < unsigned(TX) && unsigned(ly2) < unsigned(TY) && unsigned(lz2) < unsigned(TZ);
-            double* o = out0 + ((long long)pk_point(ent) * G.maxp + pk_slot(ent)) * 3;
+            // the point's partial for this tile in its own slot (point-major layout), in the
+            // arithmetic type: a wave sum of T values is exactly a T
+            T* o = reinterpret_cast<T*>(out0) + ((long long)pk_point(ent) * G.maxp + pk_slot(ent)) * 3;
             // a tile of the point's window that holds no node of its stencil: its partial is zero
             if (!__any(in)) {
-                if (lane == 0) o[0] = o[1] = o[2] = 0.0;
+                if (lane == 0) o[0] = o[1] = o[2] = T(0);
                 continue;
             }
             const int li = in ? lx2 + TX * (ly2 + TY * lz2) : 0;
@@ -469,10 +478,9 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             const T sy = wave_sum(su[1][li] * w);
             const T sz = wave_sum(su[2][li] * w);
             if (lane == 0) {
-                // the point's partial for this tile, in its own slot (point-major layout)
-                o[0] = double(sx);
-                o[1] = double(sy);
-                o[2] = double(sz);
+                o[0] = sx;
+                o[1] = sy;
+                o[2] = sz;
             }
         }
         __syncthreads();   // su is rewritten by the block's next tile

@@ -30,14 +30,14 @@ constexpr int WIN = 5;
 
 // Distinct tiles met by the WIN consecutive nodes base .. base+WIN-1 (periodic) of
 // one axis, in order of first appearance.
-__device__ __forceinline__ int axis_tiles(int base, int n, int tdim, int (&out)[WIN])
+__device__ __forceinline__ int axis_tiles(int base, int n, int lt, int (&out)[WIN])
 {
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < WIN; ++k) {
         int node = base + k;
         if (node >= n) node -= n;
-        const int t = node / tdim;
+        const int t = node >> lt;
         bool dup = false;
         for (int j = 0; j < cnt; ++j) dup |= (out[j] == t);
         if (!dup) out[cnt++] = t;
@@ -47,14 +47,14 @@ __device__ __forceinline__ int axis_tiles(int base, int n, int tdim, int (&out)[
 
 // number of distinct tiles met by the window (as axis_tiles, without the list: every index
 // is known at compile time, so nothing goes to scratch memory)
-__device__ __forceinline__ int axis_count(int base, int n, int tdim)
+__device__ __forceinline__ int axis_count(int base, int n, int lt)
 {
     int t[WIN];
 #pragma unroll
     for (int k = 0; k < WIN; ++k) {
         int node = base + k;
         if (node >= n) node -= n;
-        t[k] = node / tdim;
+        t[k] = node >> lt;
     }
     int cnt = 0;
 #pragma unroll
@@ -75,9 +75,9 @@ struct TileSet {
 // tiles of the window with bases (wx, wy, wz)
 __device__ __forceinline__ void window_tiles(const Geom& G, int wx, int wy, int wz, TileSet& s)
 {
-    s.cx = axis_tiles(wx, G.nx, G.tx, s.tx);
-    s.cy = axis_tiles(wy, G.ny, G.ty, s.ty);
-    s.cz = axis_tiles(wz, G.nz, G.tz, s.tz);
+    s.cx = axis_tiles(wx, G.nx, G.ltx, s.tx);
+    s.cy = axis_tiles(wy, G.ny, G.lty, s.ty);
+    s.cz = axis_tiles(wz, G.nz, G.ltz, s.tz);
 }
 
 // window base of one axis for a point with stencil base b (wrapped) and 1-D weights w:
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int 
         if (cx >= G.nx) cx -= G.nx;
         if (cy >= G.ny) cy -= G.ny;
         if (cz >= G.nz) cz -= G.nz;
-        const bool home = t == tile_id(G, w.w, cz / G.tz, cy / G.ty, cx / G.tx);
+        const bool home = t == tile_id(G, w.w, cz >> G.ltz, cy >> G.lty, cx >> G.ltx);
         const int slot = toff[t] + atomicAdd(&cursor[t], 1);
         tlist[slot] = int(p << PK_SHIFT) | (home ? PK_HOME : 0) | k;
     }
@@ -400,9 +400,16 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
     const long long t = (long long)c * blockDim.x + threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
     float m = 0.0f;
-    if (fp16_exp)
+    if (fp16_exp && G.smax) {
+        // one box: the slots the step kernel's tiles raised; cleared for the next step
+        for (int u = t; u < SMAX_SLOTS; u += C * blockDim.x) {
+            m = fmaxf(m, __uint_as_float(G.smax[u * SMAX_STRIDE]));
+            G.smax[u * SMAX_STRIDE] = 0u;
+        }
+    } else if (fp16_exp) {
         for (long long u = t; u < G.tiles_per_box; u += (long long)C * blockDim.x)
             m = fmaxf(m, tmax[(long long)b * G.tiles_per_box + u]);
+    }
     if (zero_net && psum) {
         for (long long u = t; u < npsum; u += (long long)C * blockDim.x)
             for (int k = 0; k < 3; ++k) s[k] += psum[3 * u + k];
@@ -514,19 +521,22 @@ struct AdvectArgs {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-// The group's sum of point p's partials (every lane of the group returns the same bits).
-__device__ __forceinline__ void group_sum(const Geom& G, const double* __restrict__ partial, long long p, int r,
+// The group's sum of point p's partials (every lane of the group returns the same bits).  The
+// partials are in the arithmetic type T of the storage (the wave sums of the step kernel);
+// the sum is taken in FP64.
+template <class T>
+__device__ __forceinline__ void group_sum(const Geom& G, const T* __restrict__ partial, long long p, int r,
                                           double (&U)[3])
 {
     // the point's partials, one per tile of its window (nt <= maxp <= 64 slots)
     const int4 win = G.win[p];
-    const int nt = axis_count(win.x, G.nx, G.tx) * axis_count(win.y, G.ny, G.ty) * axis_count(win.z, G.nz, G.tz);
-    const double* pp = partial + p * G.maxp * 3;
+    const int nt = axis_count(win.x, G.nx, G.ltx) * axis_count(win.y, G.ny, G.lty) * axis_count(win.z, G.nz, G.ltz);
+    const T* pp = partial + p * G.maxp * 3;
     double v[64 / ADV_GP][3];
 #pragma unroll
     for (int m = 0; m < 64 / ADV_GP; ++m)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) v[m][c] = r + m * ADV_GP < nt ? pp[(r + m * ADV_GP) * 3 + c] : 0.0;
+        for (int c = 0; c < 3; ++c) v[m][c] = r + m * ADV_GP < nt ? double(pp[(r + m * ADV_GP) * 3 + c]) : 0.0;
     U[0] = U[1] = U[2] = 0.0;
 #pragma unroll
     for (int m = 0; m < 64 / ADV_GP; ++m)
@@ -555,13 +565,11 @@ __device__ __forceinline__ void finish_point(const Geom& G, const AdvectArgs& A,
     }
     if (!A.advect) return;
     const int box = point_box(G, A, i);
-    const double tau = boxes[box].tau;
-    const double eta = G.rho0 * tau / 3.0;
     double inv_aL = A.inv_aL;
     if (A.mlp) inv_aL += double(A.out_scale) * double(y);
     const double R[3] = {A.pos[3 * i], A.pos[3 * i + 1], A.pos[3 * i + 2]};
     const double L[3] = {double(G.nx), double(G.ny), double(G.nz)};
-    const double mob = (A.inv_a - inv_aL) / (6.0 * M_PI * eta);
+    const double mob = (A.inv_a - inv_aL) * boxes[box].inv6pe;
     double zeta[3] = {0.0, 0.0, 0.0};
     if (A.tin) {
         // Appendix B: extra Brownian displacement, variance kT/(3 pi eta)(1/a - 1/a_L) per step
@@ -577,8 +585,9 @@ __device__ __forceinline__ void finish_point(const Geom& G, const AdvectArgs& A,
 }
 
 // Without the MLP: one group per point, lane 0 of the group finishes it.
+template <class T>
 __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
-                                                const double* __restrict__ partial)
+                                                const T* __restrict__ partial)
 {
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long i = gid / ADV_GP;
@@ -590,40 +599,64 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
 }
 
 // With the MLP correction to 1/a_L (4 -> 64 tanh -> 64 tanh -> 1, bf16 weights staged in LDS
-// as FP32, FP32 accumulation): the group of ADV_GP lanes of a point sums its partials as in
-// k_advect, then shares the network: lane r evaluates the hidden units j = r + ADV_GP q
-// (q = 0..7) of both layers, the first layer's outputs go through LDS to the whole group, and
-// a butterfly over the group adds the lanes' parts of the output.  Rows of W2 are padded to
-// 65 floats so that the group's lanes read distinct banks.
+// as FP32, FP32 accumulation).  A block of MLP_WAVES waves takes 64 points, one per lane: the
+// interpolation partials are summed first (groups of ADV_GP lanes per point, as in k_advect),
+// then wave w evaluates the first-layer units j = 16 w .. 16 w + 15 of every point into LDS,
+// reads back all 64 of its point's first-layer values, evaluates the second-layer units
+// 16 w .. 16 w + 15 with wave-uniform weights (LDS broadcasts) and its part of the output; the
+// parts are added in wave order.  tanh(s) = 1 - 2 / (exp(2 s) + 1) with the hardware exponential
+// and reciprocal (absolute error ~1e-7).
 constexpr int MLP_H = 64;
-constexpr int MLP_PAD = MLP_H + 1;
-constexpr int ADV_PTS = 256 / ADV_GP;   // points per block
+constexpr int MLP_WAVES = 4;
+constexpr int MLP_UNITS = MLP_H / MLP_WAVES;
+constexpr int MLP_BLOCK = 64 * MLP_WAVES;
 
-__global__ __launch_bounds__(256) void k_advect_mlp(const Geom G, const AdvectArgs A, const BoxDev* __restrict__ boxes,
-                                                    const double* __restrict__ partial)
+__device__ __forceinline__ float tanh_fast(float s)
 {
-    __shared__ float W1[MLP_H * 4], b1[MLP_H], W2[MLP_H * MLP_PAD], b2[MLP_H], W3[MLP_H];
-    __shared__ float h1[ADV_PTS][MLP_PAD];
+    const float e = __builtin_amdgcn_exp2f(s * 2.8853900817779268f);   // exp(2 s)
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+template <class T>
+__global__ __launch_bounds__(MLP_BLOCK) void k_advect_mlp(const Geom G, const AdvectArgs A,
+                                                          const BoxDev* __restrict__ boxes,
+                                                          const T* __restrict__ partial)
+{
+    __shared__ float4 W1[MLP_H];                         // rows of W1 (4 inputs)
+    __shared__ float b1[MLP_H], b2[MLP_H], W3[MLP_H];
+    __shared__ float4 W2[MLP_H * MLP_H / 4];             // rows of W2, 16 float4 each
+    __shared__ float h1[MLP_H][64];                      // [unit][point of the block]
+    __shared__ double Us[64][3];
+    __shared__ float ys[MLP_WAVES][64];
     __shared__ float b3;
     // lbml layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
     for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) {
         const float v = bf16_to_f32(A.mlp[k]);
-        if (k < 256) W1[k] = v;
+        if (k < 256) reinterpret_cast<float*>(W1)[k] = v;
         else if (k < 320) b1[k - 256] = v;
-        else if (k < 4416) W2[((k - 320) >> 6) * MLP_PAD + ((k - 320) & 63)] = v;
+        else if (k < 4416) reinterpret_cast<float*>(W2)[k - 320] = v;
         else if (k < 4480) b2[k - 4416] = v;
         else if (k < 4544) W3[k - 4480] = v;
         else b3 = v;
     }
+    const long long base = (long long)blockIdx.x * 64;
+    // interpolated velocity of the block's points: ADV_GP lanes per point, MLP_BLOCK / ADV_GP at a time
+    for (int pl0 = 0; pl0 < 64; pl0 += MLP_BLOCK / ADV_GP) {
+        const int pl = pl0 + int(threadIdx.x) / ADV_GP, r = int(threadIdx.x) % ADV_GP;
+        const long long i = min(base + pl, A.n - 1);
+        double U[3];
+        group_sum(G, partial, A.off + i, r, U);
+        if (r == 0) {
+            Us[pl][0] = U[0];
+            Us[pl][1] = U[1];
+            Us[pl][2] = U[2];
+        }
+    }
     __syncthreads();
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long i0 = gid / ADV_GP;
-    const int r = int(gid % ADV_GP), pl = threadIdx.x / ADV_GP;
-    const bool live = i0 < A.n;
-    const long long i = live ? i0 : A.n - 1;   // lanes past the end repeat the last point (no writes)
-    const long long p = A.off + i;
-    double U[3];
-    group_sum(G, partial, p, r, U);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const bool live = base + lane < A.n;
+    const long long i = live ? base + lane : A.n - 1;   // lanes past the end repeat the last point
     // inputs: fractional offsets of the (wrapped) position and the box's tau
     float xin[4];
     {
@@ -635,27 +668,43 @@ __global__ __launch_bounds__(256) void k_advect_mlp(const Geom G, const AdvectAr
         xin[3] = (float(boxes[point_box(G, A, i)].tau) - A.in_shift[3]) * A.in_scale[3];
     }
 #pragma unroll
-    for (int q = 0; q < MLP_H / ADV_GP; ++q) {
-        const int j = r + ADV_GP * q;
+    for (int q = 0; q < MLP_UNITS; ++q) {
+        const int j = wave * MLP_UNITS + q;
+        const float4 w = W1[j];
         float s = b1[j];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s = fmaf(W1[j * 4 + k], xin[k], s);
-        h1[pl][j] = tanhf(s);
+        s = fmaf(w.x, xin[0], s);
+        s = fmaf(w.y, xin[1], s);
+        s = fmaf(w.z, xin[2], s);
+        s = fmaf(w.w, xin[3], s);
+        h1[j][lane] = tanh_fast(s);
     }
     __syncthreads();
+    float h[MLP_H];
+#pragma unroll
+    for (int k = 0; k < MLP_H; ++k) h[k] = h1[k][lane];
     float y = 0.0f;
-#pragma unroll
-    for (int q = 0; q < MLP_H / ADV_GP; ++q) {
-        const int j = r + ADV_GP * q;
+    for (int q = 0; q < MLP_UNITS; ++q) {
+        const int j = wave * MLP_UNITS + q;
         float s = b2[j];
-#pragma unroll 16
-        for (int k = 0; k < MLP_H; ++k) s = fmaf(W2[j * MLP_PAD + k], h1[pl][k], s);
-        y = fmaf(W3[j], tanhf(s), y);
-    }
 #pragma unroll
-    for (int d = 1; d < ADV_GP; d <<= 1) y += __shfl_xor(y, d, ADV_GP);
-    y += b3;
-    if (live && r == 0) finish_point(G, A, boxes, i, p, U, y);
+        for (int k4 = 0; k4 < MLP_H / 4; ++k4) {
+            const float4 w = W2[j * (MLP_H / 4) + k4];
+            s = fmaf(w.x, h[4 * k4], s);
+            s = fmaf(w.y, h[4 * k4 + 1], s);
+            s = fmaf(w.z, h[4 * k4 + 2], s);
+            s = fmaf(w.w, h[4 * k4 + 3], s);
+        }
+        y = fmaf(W3[j], tanh_fast(s), y);
+    }
+    ys[wave][lane] = y;
+    __syncthreads();
+    if (wave == 0 && live) {
+        float yt = ys[0][lane];
+#pragma unroll
+        for (int w = 1; w < MLP_WAVES; ++w) yt += ys[w][lane];
+        const double U[3] = {Us[lane][0], Us[lane][1], Us[lane][2]};
+        finish_point(G, A, boxes, i, A.off + i, U, yt + b3);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -719,7 +768,7 @@ __global__ __launch_bounds__(256) void k_interp_points(const Geom G, long long n
     }
     T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
     if (toff) {
-        const long long t = tile_id(G, box, z / G.tz, y / G.ty, x / G.tx);
+        const long long t = tile_id(G, box, z >> G.ltz, y >> G.lty, x >> G.ltx);
         for (int k = toff[t]; k < toff[t + 1]; ++k) {
             const PRec<T>& r = rec[pk_point(tlist[k])];
             const T w = stencil_w<T>(x, r.bx, G.nx, r.wx) * stencil_w<T>(y, r.by, G.ny, r.wy) *
@@ -826,7 +875,10 @@ void launch_box_update(int storage, const Geom& G, const void* rec, const int* t
                        const double* psum, long long npsum, const float* tmax, double* part, float* pmax,
                        unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s)
 {
-    const dim3 grid(G.nboxes, G.bchunks);
+    // one box whose sums come from the records kernel and whose FP16 maximum from the slots:
+    // little to read, one block
+    const bool small = G.nboxes == 1 && (psum || !zero_net) && (G.smax || !fp16_exp);
+    const dim3 grid(G.nboxes, small ? 1 : G.bchunks);
     if (storage == ST_FP64)
         hipLaunchKernelGGL(k_box_update<double>, grid, dim3(256), 0, s, G, (const PRec<double>*)rec, toff, tlist, psum,
                            npsum, tmax, part, pmax, ticket, boxes, zero_net, fp16_exp);
@@ -836,7 +888,8 @@ void launch_box_update(int storage, const Geom& G, const void* rec, const int* t
 }
 
 
-void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, double* partial, hipStream_t s)
+void launch_advect(int storage, const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, void* partial,
+                   hipStream_t s)
 {
     if (a.n <= 0) return;
     AdvectArgs A;
@@ -858,10 +911,18 @@ void launch_advect(const Geom& G, const AdvectLaunch& a, const BoxDev* boxes, do
     A.advect = a.advect;
     A.tin = a.tin;
     const unsigned nb = nblk(a.n * ADV_GP, 256);
-    if (A.mlp)
-        hipLaunchKernelGGL(k_advect_mlp, dim3(nb), dim3(256), 0, s, G, A, boxes, (const double*)partial);
-    else
-        hipLaunchKernelGGL(k_advect, dim3(nb), dim3(256), 0, s, G, A, boxes, (const double*)partial);
+    const unsigned nbm = nblk(a.n, 64);   // with the network: 64 points per block
+    if (storage == ST_FP64) {
+        if (A.mlp)
+            hipLaunchKernelGGL(k_advect_mlp<double>, dim3(nbm), dim3(MLP_BLOCK), 0, s, G, A, boxes, (const double*)partial);
+        else
+            hipLaunchKernelGGL(k_advect<double>, dim3(nb), dim3(256), 0, s, G, A, boxes, (const double*)partial);
+    } else {
+        if (A.mlp)
+            hipLaunchKernelGGL(k_advect_mlp<float>, dim3(nbm), dim3(MLP_BLOCK), 0, s, G, A, boxes, (const float*)partial);
+        else
+            hipLaunchKernelGGL(k_advect<float>, dim3(nb), dim3(256), 0, s, G, A, boxes, (const float*)partial);
+    }
 }
 
 void launch_interp_points(int storage, const Geom& G, long long n, const double* pos, const int* boxid, double* out,

@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-fetch", required=True)
     ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--record", default=None,
+                    help="name of the record (profiles/traffic_<record>.json); default the workload's name")
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     import bench
@@ -86,14 +88,14 @@ def main():
     alg = bench.BYTES_PER_NODE[storage] * shape[0] * shape[1] * shape[2] * nboxes
     traffic = (f * scale_f + w * scale_w) * 1024
     tile, variant = bench.tuned(shape, storage, nboxes, a.workload)
-    out = dict(workload=a.workload, kernel=name, kernel_sha=bench.kernel_source_hash(),
+    out = dict(workload=a.workload, record=a.record or a.workload, kernel=name, kernel_sha=bench.kernel_source_hash(),
                tile=list(tile) if tile else None, variant=variant,
                fetch_kib_per_dispatch=f, write_kib_per_dispatch=w, dispatches=len(kf[name]),
                calibration="lb_copy_probe (16-byte non-temporal copy), %d bytes read and written" % COPY_BYTES,
                copy_fetch_kib=statistics.median(pf), copy_write_kib=statistics.median(pw),
                scale_fetch=scale_f, scale_write=scale_w, torch_copy=torch_copy,
                bytes_per_launch=traffic, algorithmic_bytes_per_launch=alg, traffic_over_algorithmic=traffic / alg)
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % a.workload)
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % (a.record or a.workload))
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))

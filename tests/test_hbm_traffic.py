@@ -26,3 +26,21 @@ def test_per_kernel_groups_counter_values_by_kernel(tmp_path):
     assert d == {"lbm::k_lattice<1>": [10.0, 12.0], "(anonymous namespace)::k_copy16": [7.0]}
     name, vals = H.pick(d, "k_copy16")
     assert name == "(anonymous namespace)::k_copy16" and vals == [7.0]
+
+
+def test_kernel_trace_table_from_a_results_database(tmp_path):
+    from paper_0707_1299_amd import kernel_trace as K
+    con = sqlite3.connect(tmp_path / "run_results.db")
+    con.execute("create table kernels (name text, duration integer)")
+    rows = [("void lbm::k_lattice<1>(lbm::Geom)", 3000000), ("void lbm::k_lattice<1>(lbm::Geom)", 3200000),
+            ("lbm::k_advect(lbm::Geom)", 20000), ("lbm::k_advect(lbm::Geom)", 30000), ("lbm::k_advect(lbm::Geom)", 25000)]
+    con.executemany("insert into kernels values (?, ?)", rows)
+    con.commit()
+    con.close()
+    rows = K.stats(str(tmp_path))
+    assert [r[0] for r in rows] == ["void lbm::k_lattice<1>", "lbm::k_advect"]
+    k, n, tot, avg, lo, hi, med, share = rows[1]
+    assert (n, tot, avg, lo, hi, med) == (3, 75.0, 25.0, 20.0, 30.0, 25.0)
+    assert abs(rows[0][7] + share - 1.0) < 1e-12
+    t = K.table(rows, match=["advect"])
+    assert "k_advect" in t and "k_lattice" not in t
