@@ -108,7 +108,12 @@ typedef struct lb_params {
                                32 = FP16 storage: one node per lane in the step
                                    kernel (by default, with nx even, each lane
                                    takes two adjacent x nodes with 32-bit
-                                   accesses).
+                                   accesses),
+                               64 = the blocks of one tile row (all tiles with the
+                                   same y, z tile index) run back to back on one
+                                   XCD, tile rows in launch order across the XCDs
+                                   (overrides 16; where the blocks per tile row are
+                                   not a power of two, launch order).
                                With LB_STORAGE_MOM32 bits 0 and 1 have no effect: each
                                node gathers the pieces of its 18 neighbours with cached
                                buffer loads. */

@@ -93,7 +93,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_MOM32) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
-    if (p->variant < 0 || p->variant > 63) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if (p->variant < 0 || p->variant > 127) { why = "unknown kernel variant"; return LB_ERR_ARG; }
     if (p->collision < LB_COLLISION_PROJECTED || p->collision > LB_COLLISION_MRT) {
         why = "unknown collision operator";
         return LB_ERR_ARG;
@@ -138,6 +138,11 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
                   "box of under 4 GiB";
             return LB_ERR_ARG;
         }
+        // two FP16 nodes per lane on whole-wave rows address each z plane of rows from one descriptor
+        if (pairs && lanes_x >= 64 && (unsigned long long)p->ny * G.rb * storage_bytes(p->storage) >= (1ULL << 32)) {
+            why = "two FP16 nodes per lane need a z plane (ny * nx nodes) of under 4 GiB";
+            return LB_ERR_SIZE;
+        }
     }
     G.tiles_per_box = (long long)G.ntx * G.nty * G.ntz;
     G.ntiles = G.tiles_per_box * p->nboxes;
@@ -153,6 +158,16 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.bchunks = int(std::min<long long>(256, (G.tiles_per_box + 255) / 256));
     G.tpb = 1 << ((p->variant >> 2) & 3);
     G.order = (p->variant >> 4) & 1;
+    G.lgrp = 0;
+    if ((p->variant >> 6) & 1) {
+        // the runs of one tile row on one XCD: needs a power-of-two count of whole runs per row
+        // (otherwise launch order)
+        G.order = 1;
+        if (G.ntx % G.tpb == 0 && ((G.ntx / G.tpb) & (G.ntx / G.tpb - 1)) == 0) {
+            G.order = 2;
+            G.lgrp = __builtin_ctz(unsigned(G.ntx / G.tpb));
+        }
+    }
     G.pairs = p->storage == LB_STORAGE_FP16 && p->nx % 2 == 0 && !((p->variant >> 5) & 1);
     G.coll = p->kT > 0.0 ? 2 : (p->collision != LB_COLLISION_PROJECTED ? 1 : 0);
     G.seed_lo = uint32_t(p->seed);

@@ -103,7 +103,9 @@ struct Geom {
     int maxp;             // most tiles met by one point's binning window (5 nodes per axis)
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
-    int order;            // 0: blocks renumbered into contiguous runs per XCD; 1: launch order
+    int order;            // 0: blocks renumbered into contiguous runs per XCD; 1: launch order;
+                          // 2: launch order of tile rows, the runs of one tile row on one XCD
+    int lgrp;             // order 2: base-2 logarithm of the runs per tile row
     int pairs;            // FP16 step: two adjacent x nodes per lane (nx even)
     int* nf;              // per box, sticky: non-finite value or FP16 overflow seen by a step
     int* rebin;           // set when a point's stencil has left its binning window (tile lists stale)
@@ -131,6 +133,20 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     const int q = nblocks >> 3, r = nblocks & 7;
     const int xcd = b & 7, j = b >> 3;
     return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
+}
+
+// Run of block b when the 2^lg runs of each tile row go to one XCD back to back while
+// the tile rows themselves still advance in launch order across the XCDs: the k-th
+// block the dispatcher sends to XCD j (b = 8k + j) takes run (k mod 2^lg) of tile row
+// 8 (k div 2^lg) + j.  The x-neighbours a tile's pull reads at its edges are then in
+// the L2 of the XCD that reads them.  Blocks past the last whole group of 8 tile rows
+// keep their own run (the map is a bijection on [0, nblocks)).
+__device__ __forceinline__ int row_group_run(int b, int nblocks, int lg)
+{
+    const int whole = (nblocks >> (lg + 3)) << (lg + 3);
+    if (b >= whole) return b;
+    const int k = b >> 3, j = b & 7;
+    return ((((k >> lg) << 3) + j) << lg) + (k & ((1 << lg) - 1));
 }
 
 // One-dimensional weight of a stencil whose first node is `base` at node
@@ -330,20 +346,27 @@ __device__ __forceinline__ void store_pop(S v, S* __restrict__ db, long long rb,
 
 // FP16 storage, two nodes per lane: the stored values of population k at nodes
 // x and x + 1 (x even, nx even) form one 32-bit word, node x in the low half.
-// Same addressing modes as load_pop with 32-bit accesses.
+// Same addressing modes as load_pop with 32-bit accesses, except that A_ROW takes
+// one descriptor per z plane of rows (a pull's upstream rows lie in three planes)
+// and puts the row within the plane into the scalar offset: three descriptors
+// instead of nine keep the kernel within the scalar registers (a z plane of a box
+// is under 4 GiB, checked at set-up).
 template <bool NTL, int ADDR>
 __device__ __forceinline__ uint32_t load_pair(const _Float16* __restrict__ sb, long long rb, long long kp,
-                                              unsigned box_bytes, int k, unsigned row, int x)
+                                              unsigned box_bytes, int ny, int k, unsigned sz, unsigned sy, int x)
 {
     constexpr int AUX = NTL ? 2 : 0;
     if constexpr (ADDR == A_ROW) {
-        const unsigned srow = __builtin_amdgcn_readfirstlane(row);
-        return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(row_block(sb, rb, srow), unsigned(rb) * 2u),
-                                                    unsigned(x) * 2u, unsigned(k) * unsigned(kp) * 2u, AUX);
+        const unsigned z = __builtin_amdgcn_readfirstlane(sz), y = __builtin_amdgcn_readfirstlane(sy);
+        const unsigned rbb = unsigned(rb) * 2u;
+        return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(row_block(sb, rb, z * unsigned(ny)), unsigned(ny) * rbb),
+                                                    unsigned(x) * 2u, y * rbb + unsigned(k) * unsigned(kp) * 2u, AUX);
     } else if constexpr (ADDR == A_BOX32) {
+        const unsigned row = sz * unsigned(ny) + sy;
         return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(sb, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * 2u,
                                                     unsigned(k) * unsigned(kp) * 2u, AUX);
     } else {
+        const unsigned row = sz * unsigned(ny) + sy;
         const uint32_t* p = reinterpret_cast<const uint32_t*>(sb + pop_index(rb, kp, k, row, x));
         if constexpr (NTL)
             return __builtin_nontemporal_load(p);
@@ -354,16 +377,19 @@ __device__ __forceinline__ uint32_t load_pair(const _Float16* __restrict__ sb, l
 
 template <int ADDR>
 __device__ __forceinline__ void store_pair(uint32_t v, _Float16* __restrict__ db, long long rb, long long kp,
-                                           unsigned box_bytes, int k, unsigned row, int x)
+                                           unsigned box_bytes, int ny, int k, unsigned z, unsigned y, int x)
 {
     if constexpr (ADDR == A_ROW) {
-        const unsigned srow = __builtin_amdgcn_readfirstlane(row);
-        __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(row_block(db, rb, srow), unsigned(rb) * 2u),
-                                              unsigned(x) * 2u, unsigned(k) * unsigned(kp) * 2u, 2);
+        const unsigned sz = __builtin_amdgcn_readfirstlane(z), sy = __builtin_amdgcn_readfirstlane(y);
+        const unsigned rbb = unsigned(rb) * 2u;
+        __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(row_block(db, rb, sz * unsigned(ny)), unsigned(ny) * rbb),
+                                              unsigned(x) * 2u, sy * rbb + unsigned(k) * unsigned(kp) * 2u, 2);
     } else if constexpr (ADDR == A_BOX32) {
+        const unsigned row = z * unsigned(ny) + y;
         __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(db, box_bytes), unsigned(pop_index(rb, kp, 0, row, x)) * 2u,
                                               unsigned(k) * unsigned(kp) * 2u, 2);
     } else {
+        const unsigned row = z * unsigned(ny) + y;
         __builtin_nontemporal_store(v, reinterpret_cast<uint32_t*>(db + pop_index(rb, kp, k, row, x)));
     }
 }
@@ -394,11 +420,10 @@ __device__ __forceinline__ void pull_pairs(const _Float16* __restrict__ sb, long
         const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
         const int sy = cy > 0 ? ym : (cy < 0 ? yp : y);
         const int sz = cz > 0 ? zm : (cz < 0 ? zp : z);
-        const unsigned row = unsigned(sz) * unsigned(ny) + unsigned(sy);
-        own[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, i, row, x);
+        own[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, ny, i, unsigned(sz), unsigned(sy), x);
         if (cx != 0) {
             const int xe = LX >= 64 ? (cx > 0 ? el : er) : (cx > 0 ? xl : xr);
-            edge[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, i, row, xe);
+            edge[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, ny, i, unsigned(sz), unsigned(sy), xe);
         }
     }
     const bool first = lane == 0;
@@ -411,14 +436,16 @@ __device__ __forceinline__ void pull_pairs(const _Float16* __restrict__ sb, long
         } else if (cx > 0) {
             uint32_t prev = edge[i];
             if constexpr (LX >= 64) {
-                prev = __builtin_amdgcn_update_dpp(0u, own[i], 0x138, 0xf, 0xf, false);   // wave_shr:1
+                // wave_shr:1; lane 0 (no source, bound_ctrl gives 0) takes the edge word below
+                prev = uint32_t(__builtin_amdgcn_mov_dpp(int(own[i]), 0x138, 0xf, 0xf, true));
                 if (first) prev = edge[i];
             }
             w[i] = __builtin_amdgcn_alignbit(own[i], prev, 16);    // (prev.hi, own.lo)
         } else {
             uint32_t next = edge[i];
             if constexpr (LX >= 64) {
-                next = __builtin_amdgcn_update_dpp(0u, own[i], 0x130, 0xf, 0xf, false);   // wave_shl:1
+                // wave_shl:1; lane 63 likewise
+                next = uint32_t(__builtin_amdgcn_mov_dpp(int(own[i]), 0x130, 0xf, 0xf, true));
                 if (last) next = edge[i];
             }
             w[i] = __builtin_amdgcn_alignbit(next, own[i], 16);    // (own.hi, next.lo)

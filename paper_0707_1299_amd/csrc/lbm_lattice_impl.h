@@ -115,6 +115,8 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     bool bad = false;
     T mx = 0;                     // FP16: largest |f*_i / w_i| of the lane's nodes
     T uxs[NPL], uys[NPL], uzs[NPL];
+    const T gcx = T(B.gc[0]), gcy = T(B.gc[1]), gcz = T(B.gc[2]);   // the box's counter-force density
+    const T rho0 = T(G.rho0), tau = T(B.tau), om = T(B.omega);         // converted once per lane
 
     // ---- per node of the lane: moments, force, collision, post-collision values
 #pragma unroll
@@ -146,7 +148,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         }
 
         // ---- force density at this node: counter-force + the tile's points
-        T gx = T(B.gc[0]), gy = T(B.gc[1]), gz = T(B.gc[2]);
+        T gx = gcx, gy = gcy, gz = gcz;
         if (h == 0 && toff) {
             k0 = toff[tile];
             k1 = toff[tile + 1];
@@ -166,7 +168,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             gz += r.f[2] * w;
         }
 
-        const T rho = T(G.rho0) + drho;
+        const T rho = rho0 + drho;
         // FP16 storage: the hardware reciprocal (1 ulp), far below the storage's rounding
         T ir;
         if constexpr (ST == ST_FP16)
@@ -251,7 +253,6 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                 br[i] = kg * (f[i] * inv_w - hb);
             }
         }
-        const T tau = T(B.tau), om = T(B.omega);
         T Bxx, Byy, Bzz;
         if constexpr (COLL) {
             // shear drivers of the diagonal; their trace relaxes at omega_b instead (bulk mode)
@@ -410,7 +411,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 #pragma unroll
             for (int i = 0; i < NQ; ++i)
                 store_pair<ADDR>(__builtin_bit_cast(uint32_t, opair[i]), reinterpret_cast<_Float16*>(db), G.rb, G.kp,
-                                 box_bytes, i, row, x);
+                                 box_bytes, G.ny, i, unsigned(z), unsigned(y), x);
         }
     }
     if constexpr (ST == ST_FP16) {
@@ -487,13 +488,16 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     }
 }
 
-// One block per run of G.tpb consecutive tiles (unless G.order is set, blocks are
-// renumbered so that the runs of one XCD are contiguous); each tile is finished
-// before the next.  BLOCK / NPL threads per block.
+// One block per run of G.tpb consecutive tiles, in the block order G.order names
+// (launch order, contiguous runs per XCD, or tile rows kept on one XCD); each tile is
+// finished before the next.  BLOCK / NPL threads per block.
 // With COLL == 2 the block of tile 0 also advances the step counter for the next
 // step (*tout = *tin + 1; the two slots alternate with the population copies).
+// Two FP16 nodes per lane, projected collision, buffer addressing: at most 80 VGPRs (six
+// waves per SIMD instead of five at the 84 the compiler picks unbounded, with no spills),
+// since this step waits mostly on memory.  The other forms would spill under that bound.
 template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1>
-__global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
+__global__ __launch_bounds__(BLOCK / NPL, NPL == 2 && COLL == 0 && !(VAR & 1) ? 6 : 1) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
                                                    const BoxDev* __restrict__ boxes, const int* __restrict__ toff,
                                                    const int* __restrict__ tlist,
@@ -502,7 +506,8 @@ __global__ __launch_bounds__(BLOCK) void k_lattice(const Geom G, const typename 
                                                    const unsigned long long* __restrict__ tin,
                                                    unsigned long long* __restrict__ tout)
 {
-    const int first = (G.order ? int(blockIdx.x) : xcd_tile(blockIdx.x, gridDim.x)) * G.tpb;
+    const int b = int(blockIdx.x), nb = int(gridDim.x);
+    const int first = (G.order == 1 ? b : G.order == 0 ? xcd_tile(b, nb) : row_group_run(b, nb, G.lgrp)) * G.tpb;
     const int last = min((long long)first + G.tpb, G.ntiles);
     for (int tile = first; tile < last; ++tile)
         lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL, NPL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1, tin);

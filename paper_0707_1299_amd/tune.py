@@ -22,7 +22,7 @@ CACHE = os.path.join(HERE, "tune_cache.json")
 ARCH = "gfx950"
 TILES = [(64, 2, 2), (64, 4, 1), (64, 1, 4), (128, 2, 1), (128, 1, 2), (256, 1, 1), (32, 4, 2), (32, 2, 4),
          (16, 4, 4)]
-VARIANTS = [0, 2, 4, 6, 8, 10, 16, 18, 20, 22]
+VARIANTS = [0, 2, 4, 6, 8, 10, 16, 18, 20, 22, 66, 70]
 
 
 def key(shape, storage, nboxes, tag=None):
@@ -66,6 +66,8 @@ def candidates(shape, storage="fp32"):
             lanes = t[0] // (1 if v & 32 else npl)        # bit 32: one FP16 node per lane
             if t[0] > 2 * nx or (big and lanes < 64):
                 continue
+            if v & 64 and nx // t[0] < 2 * (1 << ((v >> 2) & 3)):
+                continue        # one run per tile row: the same block order as launch order
             out.append((t, v))
     return out
 

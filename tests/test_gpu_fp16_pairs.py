@@ -65,6 +65,7 @@ CASES = [
     ((10, 8, 64), (64, 2, 2), 4),       # two tiles per block
     ((10, 9, 34), (16, 4, 4), 0),       # 8 lanes per tile row, ragged in every axis
     ((8, 8, 64), (64, 4, 1), 1),        # 64-bit addressing
+    ((11, 6, 256), (64, 2, 2), 66),     # the two tiles of a tile row on one XCD, 33 tile rows
 ]
 
 

@@ -86,7 +86,8 @@ def test_stokeslet_32cubed_500_steps(storage):
     ("fp32", (128, 2, 1), 8), ("fp32", (32, 2, 4), 14), ("fp64", (16, 4, 4), 12), ("mom32", None, 0),
     ("mom32", (16, 4, 4), 2), ("mom32", (64, 1, 4), 1), ("mom32", (128, 1, 2), 6), ("mom32", (32, 2, 4), 14),
     ("mom32", (64, 2, 2), 8), ("fp32", (128, 2, 1), 16), ("fp32", (64, 4, 1), 22), ("fp64", (32, 4, 2), 18),
-    ("mom32", (128, 1, 2), 20)])
+    ("mom32", (128, 1, 2), 20), ("fp32", (64, 2, 2), 66), ("fp64", (64, 1, 4), 70), ("mom32", (64, 4, 1), 64),
+    ("fp32", (16, 4, 4), 66)])
 def test_ragged_multi_tile_forces_zero_net(storage, tile, variant):
     """Non-cubic box with ragged tiles on every axis, forces near the periodic seams."""
     shape = (13, 10, 70)
@@ -307,8 +308,8 @@ def test_kernel_variants_bitwise_equal(storage):
     sets = [(pos, frc, lbm.LB_FORCES_STATIC, None, None)]
     ref = None
     t0 = (64, 2, 2)
-    cases = ((t0, 0), (t0, 1), (t0, 2), (t0, 3), (t0, 4), (t0, 10), (t0, 12), (t0, 16), (t0, 22),
-             ((128, 2, 1), 1), ((128, 2, 1), 16))
+    cases = ((t0, 0), (t0, 1), (t0, 2), (t0, 3), (t0, 4), (t0, 10), (t0, 12), (t0, 16), (t0, 22), (t0, 66),
+             (t0, 70), ((128, 2, 1), 1), ((128, 2, 1), 16))
     for tile, variant in cases:
         _, u, o = run_gpu((L, L, L), storage, 0.5, sets, 12, tile=tile, variant=variant)
         if ref is None:
