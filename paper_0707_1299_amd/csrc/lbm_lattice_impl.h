@@ -493,11 +493,14 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 // finished before the next.  BLOCK / NPL threads per block.
 // With COLL == 2 the block of tile 0 also advances the step counter for the next
 // step (*tout = *tin + 1; the two slots alternate with the population copies).
-// Two FP16 nodes per lane, projected collision, buffer addressing: at most 80 VGPRs (six
-// waves per SIMD instead of five at the 84 the compiler picks unbounded, with no spills),
-// since this step waits mostly on memory.  The other forms would spill under that bound.
+// Two FP16 nodes per lane, projected collision, buffer addressing: this step waits mostly on
+// memory, so it asks for more waves per SIMD than the 5 the compiler's 84 VGPRs allow
+// unbounded: 7 (72 VGPRs, a few scalar registers spilled to VGPR lanes) where a wave covers a
+// tile row, 6 (80 VGPRs) for narrower rows, whose per-lane neighbour loads need more
+// registers.  Neither spills VGPRs; the other forms would under such bounds.
 template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1>
-__global__ __launch_bounds__(BLOCK / NPL, NPL == 2 && COLL == 0 && !(VAR & 1) ? 6 : 1) void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
+__global__ __launch_bounds__(BLOCK / NPL, NPL == 2 && COLL == 0 && !(VAR & 1) ? (TX / NPL >= 64 ? 7 : 6) : 1)
+void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
                                                    const BoxDev* __restrict__ boxes, const int* __restrict__ toff,
                                                    const int* __restrict__ tlist,

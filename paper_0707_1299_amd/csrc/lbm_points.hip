@@ -386,6 +386,28 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_
 //    the bins were filled.  With one box the records kernel has already summed
 //    the forces per block of points (psum, npsum blocks): those sums are added
 //    instead, in block order.
+// The box's counter-force density from its force sums (four wave sums each) and, for FP16
+// storage, the next step's scale exponent from its largest bracket magnitude.
+__device__ __forceinline__ void finish_box(const Geom& G, BoxDev& B, const double (&red)[4][3], const float (&redm)[4],
+                                           int zero_net, int fp16_exp)
+{
+    if (zero_net)
+        for (int k = 0; k < 3; ++k) B.gc[k] = -(((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]) / double(G.N);
+    if (fp16_exp) {
+        const float mx = fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3]));
+        const int e_in = B.e_data;
+        int e_out = e_in;
+        if (mx > 0.0f && mx < 3.0e38f) {
+            const float v = ldexpf(mx, e_in);
+            if (v > 32768.0f || v < 4096.0f) e_out = 13 - ilogbf(mx);
+        }
+        e_out = max(-100, min(120, e_out));
+        B.s_in = ldexpf(1.0f, -e_in);
+        B.s_out = ldexpf(1.0f, e_out);
+        B.e_data = e_out;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>* __restrict__ rec,
                                                     const int* __restrict__ toff, const int* __restrict__ tlist,
@@ -451,6 +473,12 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
     m = wave_max(m);
     if (lane == 0) redm[wave] = m;
     __syncthreads();
+    if (C == 1) {
+        // the block is the box's only one: its sums are the box's (the same values the combination
+        // below would give: it would add zeros to them), with no partials, fences or tickets
+        if (threadIdx.x == 0) finish_box(G, boxes[b], red, redm, zero_net, fp16_exp);
+        return;
+    }
     if (threadIdx.x == 0) {
         for (int k = 0; k < 3; ++k)
             part[((long long)b * C + c) * 3 + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
@@ -477,22 +505,7 @@ __global__ __launch_bounds__(256) void k_box_update(const Geom G, const PRec<T>*
     if (lane == 0) redm[wave] = mx;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    BoxDev& B = boxes[b];
-    if (zero_net)
-        for (int k = 0; k < 3; ++k) B.gc[k] = -(((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]) / double(G.N);
-    if (fp16_exp) {
-        mx = fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3]));
-        const int e_in = B.e_data;
-        int e_out = e_in;
-        if (mx > 0.0f && mx < 3.0e38f) {
-            const float v = ldexpf(mx, e_in);
-            if (v > 32768.0f || v < 4096.0f) e_out = 13 - ilogbf(mx);
-        }
-        e_out = max(-100, min(120, e_out));
-        B.s_in = ldexpf(1.0f, -e_in);
-        B.s_out = ldexpf(1.0f, e_out);
-        B.e_data = e_out;
-    }
+    finish_box(G, boxes[b], red, redm, zero_net, fp16_exp);
     ticket[b] = 0u;
 }
 
