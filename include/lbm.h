@@ -263,11 +263,22 @@ int lb_clear_forces(lb_ctx* ctx);
  * current positions, collide every node with them (Eq. fiexp), interpolate the
  * physical velocity u at the points with the same kernel, propagate (the split
  * after Eq. halftransform), then advance colloids by the Sec. IV update
- * (explicit Euler).  Repeated chunks of 2, 4, ..., 32 steps run as captured
+ * (explicit Euler).  Repeated chunks of 2, 4, ..., 128 steps run as captured
  * HIP graphs (captured on first use per chunk length, parity and set of
  * registered forces).
  */
 int lb_step(lb_ctx* ctx, int32_t nsteps);
+
+/*
+ * Capture, without running them, the HIP graphs that lb_step(ctx, nsteps) would
+ * replay from the current state (registered sets, population parity), so that a
+ * caller who times lb_step keeps graph capture out of the timed region.  No step
+ * is taken and nothing is enqueued; the state is unchanged.  With a pending
+ * next-step set, in timing mode or for nsteps < 4 there is nothing to capture
+ * ahead (LB_OK).  Errors: LB_ERR_ARG (ctx NULL, nsteps < 0), LB_ERR_HIP (capture
+ * failed).
+ */
+int lb_prepare_steps(lb_ctx* ctx, int32_t nsteps);
 
 /*
  * Physical moments at the current time with the registered forces

@@ -5,7 +5,7 @@
 // per-point records, the tile bins and the scratch of the reductions, and
 // enqueues every kernel on the caller's stream.  Repeated steps are captured
 // once per (parity, force-set generation, length) into HIP graphs of 2, 4,
-// ..., 32 steps and replayed.
+// ..., 128 steps and replayed.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -221,7 +221,7 @@ struct Set {
 };
 
 // longest captured chunk of steps (a power of two; graphs of 2, 4, ..., GRAPH_MAX steps)
-constexpr int GRAPH_MAX = 32;
+constexpr int GRAPH_MAX = 128;
 
 // Header of a checkpoint (see lb_checkpoint_save): what the state was taken from, and where each
 // section starts in the blob.
@@ -775,6 +775,26 @@ int lb_step(lb_ctx* c, int32_t nsteps)
     }
     c->steps += left;
     return check_async(c);
+}
+
+int lb_prepare_steps(lb_ctx* c, int32_t nsteps)
+{
+    if (!c) return LB_ERR_ARG;
+    clear_stale_error();
+    if (nsteps < 0) return fail(c, LB_ERR_ARG, "nsteps < 0");
+    // the same chunks as lb_step; a pending next-step set changes the sets after the first step
+    if (has_kind(c, LB_FORCES_NEXT_STEP) || c->timing || nsteps < 4) return LB_OK;
+    const bool rebuild = has_kind(c, LB_COLLOIDS) || has_kind(c, KIND_ELASTIC);
+    int rest = nsteps;
+    while (rest >= 2) {
+        int len = GRAPH_MAX;
+        while (len > rest) len >>= 1;
+        hipGraphExec_t exec;
+        const int r = get_graph(c, rebuild, len, &exec);
+        if (r) return r;
+        while (rest >= len) rest -= len;
+    }
+    return LB_OK;
 }
 
 static int prepare_fields(lb_ctx* c)

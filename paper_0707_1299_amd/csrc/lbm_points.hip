@@ -612,13 +612,15 @@ __global__ __launch_bounds__(256) void k_advect(const Geom G, const AdvectArgs A
 }
 
 // With the MLP correction to 1/a_L (4 -> 64 tanh -> 64 tanh -> 1, bf16 weights staged in LDS
-// as FP32, FP32 accumulation).  A block of MLP_WAVES waves takes 64 points, one per lane: the
-// interpolation partials are summed first (groups of ADV_GP lanes per point, as in k_advect),
-// then wave w evaluates the first-layer units j = 16 w .. 16 w + 15 of every point into LDS,
-// reads back all 64 of its point's first-layer values, evaluates the second-layer units
-// 16 w .. 16 w + 15 with wave-uniform weights (LDS broadcasts) and its part of the output; the
-// parts are added in wave order.  tanh(s) = 1 - 2 / (exp(2 s) + 1) with the hardware exponential
-// and reciprocal (absolute error ~1e-7).
+// as FP32, FP32 products and sums).  A block of MLP_WAVES waves takes 64 points: the
+// interpolation partials are summed first (groups of ADV_GP lanes per point, as in k_advect);
+// wave w evaluates the first-layer units j = 16 w .. 16 w + 15 of every point (one point per
+// lane) into LDS; the second layer is a 64 x 64 by 64 x 64 product on the matrix cores (FP32
+// MFMA, 32 x 32 x 2 steps): wave w takes the 32 units 32 (w & 1) .. and the 32 points
+// 32 (w >> 1) .. of one output tile, applies tanh and the output weights to its 16 values per
+// lane, and the two halves of the units are added (lanes l and l ^ 32, then the two waves of a
+// point half in order).  tanh(s) = 1 - 2 / (exp(2 s) + 1) with the hardware exponential and
+// reciprocal (absolute error ~1e-7).
 constexpr int MLP_H = 64;
 constexpr int MLP_WAVES = 4;
 constexpr int MLP_UNITS = MLP_H / MLP_WAVES;
@@ -630,6 +632,8 @@ __device__ __forceinline__ float tanh_fast(float s)
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
+typedef float mfma_acc16 __attribute__((ext_vector_type(16)));
+
 template <class T>
 __global__ __launch_bounds__(MLP_BLOCK) void k_advect_mlp(const Geom G, const AdvectArgs A,
                                                           const BoxDev* __restrict__ boxes,
@@ -637,17 +641,17 @@ __global__ __launch_bounds__(MLP_BLOCK) void k_advect_mlp(const Geom G, const Ad
 {
     __shared__ float4 W1[MLP_H];                         // rows of W1 (4 inputs)
     __shared__ float b1[MLP_H], b2[MLP_H], W3[MLP_H];
-    __shared__ float4 W2[MLP_H * MLP_H / 4];             // rows of W2, 16 float4 each
+    __shared__ float W2T[MLP_H][MLP_H + 1];              // W2 transposed: [input k][unit] (padded row)
     __shared__ float h1[MLP_H][64];                      // [unit][point of the block]
     __shared__ double Us[64][3];
-    __shared__ float ys[MLP_WAVES][64];
+    __shared__ float ys[2][64];
     __shared__ float b3;
     // lbml layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
     for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) {
         const float v = bf16_to_f32(A.mlp[k]);
         if (k < 256) reinterpret_cast<float*>(W1)[k] = v;
         else if (k < 320) b1[k - 256] = v;
-        else if (k < 4416) reinterpret_cast<float*>(W2)[k - 320] = v;
+        else if (k < 4416) W2T[(k - 320) % MLP_H][(k - 320) / MLP_H] = v;
         else if (k < 4480) b2[k - 4416] = v;
         else if (k < 4544) W3[k - 4480] = v;
         else b3 = v;
@@ -692,31 +696,30 @@ __global__ __launch_bounds__(MLP_BLOCK) void k_advect_mlp(const Geom G, const Ad
         h1[j][lane] = tanh_fast(s);
     }
     __syncthreads();
-    float h[MLP_H];
+    // second layer, one 32 x 32 tile per wave: A = W2 rows (units), B = first-layer values
+    // (columns = points); step ks takes inputs 2 ks (lanes 0-31) and 2 ks + 1 (lanes 32-63)
+    const int uh = wave & 1, ph = wave >> 1, c32 = lane & 31, kh = lane >> 5;
+    mfma_acc16 acc;
 #pragma unroll
-    for (int k = 0; k < MLP_H; ++k) h[k] = h1[k][lane];
-    float y = 0.0f;
-    for (int q = 0; q < MLP_UNITS; ++q) {
-        const int j = wave * MLP_UNITS + q;
-        float s = b2[j];
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-        for (int k4 = 0; k4 < MLP_H / 4; ++k4) {
-            const float4 w = W2[j * (MLP_H / 4) + k4];
-            s = fmaf(w.x, h[4 * k4], s);
-            s = fmaf(w.y, h[4 * k4 + 1], s);
-            s = fmaf(w.z, h[4 * k4 + 2], s);
-            s = fmaf(w.w, h[4 * k4 + 3], s);
-        }
-        y = fmaf(W3[j], tanh_fast(s), y);
+    for (int ks = 0; ks < MLP_H / 2; ++ks) {
+        const int k = 2 * ks + kh;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(W2T[k][32 * uh + c32], h1[k][32 * ph + c32], acc, 0, 0, 0);
     }
-    ys[wave][lane] = y;
+    // lane: point 32 ph + c32, units 32 uh + 8 (r / 4) + 4 kh + r % 4 of the tile
+    float y = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int u = 32 * uh + 8 * (r >> 2) + 4 * kh + (r & 3);
+        y = fmaf(W3[u], tanh_fast(acc[r] + b2[u]), y);
+    }
+    y += __shfl_xor(y, 32);
+    if (kh == 0) ys[uh][32 * ph + c32] = y;
     __syncthreads();
     if (wave == 0 && live) {
-        float yt = ys[0][lane];
-#pragma unroll
-        for (int w = 1; w < MLP_WAVES; ++w) yt += ys[w][lane];
         const double U[3] = {Us[lane][0], Us[lane][1], Us[lane][2]};
-        finish_point(G, A, boxes, i, A.off + i, U, yt + b3);
+        finish_point(G, A, boxes, i, A.off + i, U, (ys[0][lane] + ys[1][lane]) + b3);
     }
 }
 

@@ -114,6 +114,7 @@ def _load():
         "lb_clear_forces": (ctypes.c_int, [vp]),
         "lb_add_elastic": (ctypes.c_int, [vp, P(lb_elastic)]),
         "lb_step": (ctypes.c_int, [vp, i32]),
+        "lb_prepare_steps": (ctypes.c_int, [vp, i32]),
         "lb_moments": (ctypes.c_int, [vp, vp, vp]),
         "lb_interp_velocity": (ctypes.c_int, [vp, i64, vp, vp, vp]),
         "lb_diagnostics": (ctypes.c_int, [vp, P(dbl)]),
@@ -333,6 +334,10 @@ class Lattice:
 
     def step(self, n=1):
         self._check(_L.lb_step(self.ctx, n))
+
+    def prepare_steps(self, n):
+        """Capture the HIP graphs step(n) would replay, without taking a step."""
+        self._check(_L.lb_prepare_steps(self.ctx, n))
 
     def moments(self, rho=True):
         t = self.torch

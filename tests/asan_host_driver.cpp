@@ -81,6 +81,7 @@ static void entry_argument_checks()
     CHECK(lb_init(&p, nullptr, 0, nullptr, nullptr) == LB_ERR_ARG);
     CHECK(lb_set_stream(nullptr, nullptr) == LB_ERR_ARG);
     CHECK(lb_step(nullptr, 1) == LB_ERR_ARG);
+    CHECK(lb_prepare_steps(nullptr, 8) == LB_ERR_ARG);
     CHECK(lb_moments(nullptr, nullptr, nullptr) == LB_ERR_ARG);
     CHECK(lb_interp_velocity(nullptr, 1, nullptr, nullptr, nullptr) == LB_ERR_ARG);
     CHECK(lb_add_point_forces(nullptr, 1, nullptr, nullptr, nullptr, LB_FORCES_STATIC, nullptr) == LB_ERR_ARG);

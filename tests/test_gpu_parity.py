@@ -469,3 +469,30 @@ def test_fp16_exponent_adapts_and_stays_finite():
     e = rel(ug.cpu().numpy()[0], uo)
     print("fp16 adaptive exponent: u rel %.3e" % e)
     assert e <= FP16_BOUND["u"]
+
+
+def test_prepared_graphs_equal_graphs_captured_on_use():
+    """lb_prepare_steps captures the graphs of a later lb_step without taking a step; the run
+    that replays them equals the run that captures them on use, bit for bit."""
+    pos, frc = workloads.colloids(32, 20)
+    frc[:, 2] = -1e-5
+    model = dict(inv_a=1 / 0.117, inv_aL=0.77)
+    outs = []
+    for prepare in (False, True):
+        lat = lbm.Lattice((32, 32, 32), "fp32", tau=0.6, zero_net_force=True, max_points=20)
+        p = torch.tensor(pos, dtype=torch.float64, device="cuda")
+        lat.add_point_forces(p, torch.tensor(frc, dtype=torch.float64, device="cuda"), None, lbm.LB_COLLOIDS,
+                             lbm.PointModel(**model))
+        lat.step(3)
+        if prepare:
+            before = lat.steps_taken()
+            lat.prepare_steps(200)
+            assert lat.steps_taken() == before
+        lat.step(200)
+        _, u = lat.moments(rho=False)
+        lat.sync()
+        outs.append((u.cpu().numpy(), p.cpu().numpy(), lat.steps_taken()))
+        lat.close()
+    assert outs[0][2] == outs[1][2] == 203
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
