@@ -519,7 +519,30 @@ def headline(a):
         del box
         out["error_vs_oracle"] = errs
         out["oracle_cpu"] = cpu_model()
-    print(json.dumps(out))
+    return out
+
+
+def all_workloads():
+    """Every other workload, timed like the headline's forms (reported under 'workloads')."""
+    extra = {}
+    for name, steps, mlp in (("singularities128", 2000, False),
+                             ("colloids256_fp32", 300, False), ("colloids256_fp16", 300, False),
+                             ("colloids256_fp64", 200, False), ("colloids512_fp32", 100, False),
+                             ("colloids512_fp16", 100, False), ("colloids512_fp16", 100, True),
+                             ("boxes512x32_fp32", 300, False), ("boxes512x32_fp16", 300, False),
+                             ("singularities128_mom32", 2000, False), ("colloids256_mom32", 300, False),
+                             ("colloids512_mom32", 100, False), ("boxes512x32_mom32", 300, False),
+                             ("singularities128_bgk", 2000, False), ("singularities128_mrt", 2000, False),
+                             ("singularities128_fp16_bgk", 2000, False), ("singularities128_thermal", 2000, False),
+                             ("colloids256_thermal", 300, False), ("droplets256", 300, False),
+                             ("chains256", 300, False), ("slab512x512x64_fp32", 300, False),
+                             ("slab512x512x64_fp16", 300, False)):
+        rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
+        rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
+        extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                                 for k, v in rr.items()}
+        print("workload %s done" % name, file=sys.stderr, flush=True)
+    return extra
 
 
 def main():
@@ -568,7 +591,10 @@ def main():
     a.warmup = a.warmup if a.warmup is not None else (20 if hl else 200)
     a.timing_steps = a.timing_steps if a.timing_steps is not None else (50 if hl else 500)
     if hl:
-        headline(a)
+        out = headline(a)
+        if a.all:
+            out["workloads"] = all_workloads()
+        print(json.dumps(out))
         return
     if a.mlp and WORKLOADS[a.workload][3] not in ("colloids", "slab"):
         print("--mlp applies to the colloid workloads only", file=sys.stderr)
@@ -624,24 +650,7 @@ def main():
         out["error_vs_oracle"] = {"velocity_rel_linf": err, "steps": csteps}
 
     if a.all:
-        extra = {}
-        for name, steps, mlp in (("colloids256_fp32", 300, False), ("colloids256_fp16", 300, False),
-                                 ("colloids256_fp64", 200, False), ("colloids512_fp32", 100, False),
-                                 ("colloids512_fp16", 100, False), ("colloids512_fp16", 100, True),
-                                 ("boxes512x32_fp32", 300, False), ("boxes512x32_fp16", 300, False),
-                                 ("singularities128_mom32", 2000, False), ("colloids256_mom32", 300, False),
-                                 ("colloids512_mom32", 100, False), ("boxes512x32_mom32", 300, False),
-                                 ("singularities128_bgk", 2000, False), ("singularities128_mrt", 2000, False),
-                                 ("singularities128_fp16_bgk", 2000, False), ("singularities128_thermal", 2000, False),
-                                 ("colloids256_thermal", 300, False), ("droplets256", 300, False),
-                                 ("chains256", 300, False), ("slab512x512x64_fp32", 300, False),
-                                 ("slab512x512x64_fp16", 300, False)):
-            rr, _ = run_workload(name, steps, 20, 50, mlp=mlp)
-            rr["workload"] = describe(name, rr) + (" + MLP mobility correction" if mlp else "")
-            extra[name + ("+mlp" if mlp else "")] = {k: (round(v, 4) if isinstance(v, float) else v)
-                                                     for k, v in rr.items()}
-            print("workload %s done" % name, file=sys.stderr, flush=True)
-        out["workloads"] = extra
+        out["workloads"] = all_workloads()
         if not a.no_cpu:
             out["oracle_rates"] = oracle_rates()
     print(json.dumps(out))

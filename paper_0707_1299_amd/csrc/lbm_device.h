@@ -218,6 +218,21 @@ __device__ __forceinline__ T wave_max(T v)
     return lane63(v);
 }
 
+// Maximum over the 64 lanes of non-negative floats (or NaN), returned to every lane: such
+// floats order as their bit patterns, so the tree of wave_max runs on integers (one DPP
+// integer max per level; fmax would first quiet each operand).
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    unsigned u = __float_as_uint(v);
+    u = max(u, unsigned(__builtin_amdgcn_update_dpp(0, int(u), 0x111, 0xf, 0xf, true)));
+    u = max(u, unsigned(__builtin_amdgcn_update_dpp(0, int(u), 0x112, 0xf, 0xf, true)));
+    u = max(u, unsigned(__builtin_amdgcn_update_dpp(0, int(u), 0x114, 0xf, 0xf, true)));
+    u = max(u, unsigned(__builtin_amdgcn_update_dpp(0, int(u), 0x118, 0xf, 0xf, true)));
+    u = max(u, unsigned(__builtin_amdgcn_update_dpp(0, int(u), 0x142, 0xa, 0xf, false)));
+    u = max(u, unsigned(__builtin_amdgcn_update_dpp(0, int(u), 0x143, 0xc, 0xf, false)));
+    return __uint_as_float(unsigned(__builtin_amdgcn_readlane(int(u), 63)));
+}
+
 // Peskin's 4-point kernel at the four nodes floor(r)-1 .. floor(r)+2 for a
 // point at fractional offset f = r - floor(r) in [0, 1): Eq. deltadef at
 // distances 1+f, f, 1-f, 2-f, which share the root q = sqrt(1 + 4f - 4f^2).

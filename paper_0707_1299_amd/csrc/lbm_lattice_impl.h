@@ -418,7 +418,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         constexpr bool FOLD = COLL == 0 && NPL == 2;
         T m = valid ? mx : T(0);
         bad = bad || ((FOLD ? m : m * B.s_out) > T(65504));
-        m = wave_max(m);
+        m = wave_max_nonneg(m);   // m = |f*| magnitudes: non-negative
         __shared__ float wm[NW];
         if (lane == 0) wm[wave] = m;
         __syncthreads();
