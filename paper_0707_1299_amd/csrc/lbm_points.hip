@@ -646,15 +646,15 @@ __global__ __launch_bounds__(MLP_BLOCK) void k_advect_mlp(const Geom G, const Ad
     __shared__ double Us[64][3];
     __shared__ float ys[2][64];
     __shared__ float b3;
-    // lbml layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]
-    for (int k = threadIdx.x; k < LBML_NPARAM_DEV; k += blockDim.x) {
-        const float v = bf16_to_f32(A.mlp[k]);
-        if (k < 256) reinterpret_cast<float*>(W1)[k] = v;
-        else if (k < 320) b1[k - 256] = v;
-        else if (k < 4416) W2T[(k - 320) % MLP_H][(k - 320) / MLP_H] = v;
-        else if (k < 4480) b2[k - 4416] = v;
-        else if (k < 4544) W3[k - 4480] = v;
-        else b3 = v;
+    // lbml layout: W1[64][4], b1[64], W2[64][64], b2[64], W3[1][64], b3[1]; the block's share of
+    // the weights is loaded first and staged after the interpolation sums below, so that the two
+    // sets of loads are in flight together
+    constexpr int WPT = (LBML_NPARAM_DEV + MLP_BLOCK - 1) / MLP_BLOCK;
+    uint16_t wraw[WPT];
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const int k = int(threadIdx.x) + j * MLP_BLOCK;
+        wraw[j] = k < LBML_NPARAM_DEV ? A.mlp[k] : uint16_t(0);
     }
     const long long base = (long long)blockIdx.x * 64;
     // interpolated velocity of the block's points: ADV_GP lanes per point, MLP_BLOCK / ADV_GP at a time
@@ -668,6 +668,18 @@ __global__ __launch_bounds__(MLP_BLOCK) void k_advect_mlp(const Geom G, const Ad
             Us[pl][1] = U[1];
             Us[pl][2] = U[2];
         }
+    }
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const int k = int(threadIdx.x) + j * MLP_BLOCK;
+        if (k >= LBML_NPARAM_DEV) continue;
+        const float v = bf16_to_f32(wraw[j]);
+        if (k < 256) reinterpret_cast<float*>(W1)[k] = v;
+        else if (k < 320) b1[k - 256] = v;
+        else if (k < 4416) W2T[(k - 320) % MLP_H][(k - 320) / MLP_H] = v;
+        else if (k < 4480) b2[k - 4416] = v;
+        else if (k < 4544) W3[k - 4480] = v;
+        else b3 = v;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
