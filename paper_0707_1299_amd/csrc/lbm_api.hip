@@ -26,6 +26,16 @@ constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Multiplier and shift for n / d with n < 2^31 (d >= 1): s = 31 + ceil(log2 d), m = ceil(2^s / d)
+// (below 2^32 for every d >= 1); then n / d = (n * m) >> s exactly.
+void set_div_magic(int d, unsigned& m, int& s)
+{
+    int l = 0;
+    while ((1LL << l) < d) ++l;
+    s = 31 + l;
+    m = unsigned(((1ULL << s) + (unsigned long long)d - 1) / (unsigned long long)d);
+}
+
 size_t storage_bytes(int st) { return st == LB_STORAGE_FP64 ? 8 : (st == LB_STORAGE_FP16 ? 2 : 4); }
 
 size_t rec_bytes(int st) { return st == LB_STORAGE_FP64 ? sizeof(PRec<double>) : sizeof(PRec<float>); }
@@ -123,6 +133,9 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.ntx = (p->nx + tx - 1) / tx;
     G.nty = (p->ny + ty - 1) / ty;
     G.ntz = (p->nz + tz - 1) / tz;
+    set_div_magic(G.ntx, G.mtx, G.stx);
+    set_div_magic(G.nty, G.mty, G.sty);
+    set_div_magic(G.ntz, G.mtz, G.stz);
     G.N = (long long)p->nx * p->ny * p->nz;
     G.kp = p->nx;
     G.rb = (long long)planes_of(p->storage) * p->nx;

@@ -100,6 +100,8 @@ struct Geom {
     int tx, ty, tz;       // tile extent per axis (tx * ty * tz == BLOCK), powers of two
     int ltx, lty, ltz;    // their base-2 logarithms
     int ntx, nty, ntz;    // tiles per axis
+    unsigned mtx, mty, mtz;   // for n < 2^31: n / nt = (n * m) >> s (multipliers and shifts set
+    int stx, sty, stz;        // on the host, so the step kernel divides without a reciprocal)
     int maxp;             // most tiles met by one point's binning window (5 nodes per axis)
     int bchunks;          // blocks per box of the per-box force / maximum reductions
     int tpb;              // tiles per block of the step kernel
@@ -128,6 +130,13 @@ struct Geom {
 // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD
 // works through a contiguous run of tiles (neighbouring tiles share cache
 // lines of the x-shifted pulls and are then served by the same L2).
+// n / d for n < 2^31 with the multiplier m = ceil(2^s / d), s = 31 + ceil(log2 d), that the
+// host computes: the product's error stays below one part in 2^31 of the quotient's unit.
+__device__ __forceinline__ unsigned div_magic(unsigned n, unsigned m, int s)
+{
+    return unsigned(((unsigned long long)n * m) >> s);
+}
+
 __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 {
     const int q = nblocks >> 3, r = nblocks & 7;

@@ -59,15 +59,15 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     constexpr int LX = TX / NPL;              // lanes along x in a tile row
     constexpr int NW = BLOCK / NPL / 64;      // waves per block
 
-    // (unsigned: divisions by the tile counts are then a multiply-high and a shift in the
-    // scalar unit, with no sign corrections)
-    unsigned t = unsigned(tile);
-    const int itx = int(t % unsigned(G.ntx));
-    t /= unsigned(G.ntx);
-    const int ity = int(t % unsigned(G.nty));
-    t /= unsigned(G.nty);
-    const int itz = int(t % unsigned(G.ntz));
-    const int box = int(t / unsigned(G.ntz));
+    // (the divisions by the tile counts use multipliers set on the host: a 64-bit product and a
+    // shift in the scalar unit, with no reciprocal to set up in the kernel)
+    const unsigned t0 = unsigned(tile);
+    const unsigned t1 = div_magic(t0, G.mtx, G.stx), t2 = div_magic(t1, G.mty, G.sty);
+    const unsigned t3 = div_magic(t2, G.mtz, G.stz);
+    const int itx = int(t0 - t1 * unsigned(G.ntx));
+    const int ity = int(t1 - t2 * unsigned(G.nty));
+    const int itz = int(t2 - t3 * unsigned(G.ntz));
+    const int box = int(t3);
     // a tile row of at least 64 lanes puts each wave on one row: y and z are then wave-uniform
     // and live in scalar registers (so do the upstream row indices of the pull)
     const int tid_w = LX >= 64 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x)) : int(threadIdx.x);
