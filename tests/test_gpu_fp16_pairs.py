@@ -66,6 +66,8 @@ CASES = [
     ((10, 9, 34), (16, 4, 4), 0),       # 8 lanes per tile row, ragged in every axis
     ((8, 8, 64), (64, 4, 1), 1),        # 64-bit addressing
     ((11, 6, 256), (64, 2, 2), 66),     # the two tiles of a tile row on one XCD, 33 tile rows
+    ((9, 7, 512), (128, 2, 1), 82),     # 4 tiles per tile row on one XCD, 36 rows (4 past the last group of 8)
+    ((10, 8, 512), (128, 2, 1), 86),    # 2 runs of 2 tiles per tile row on one XCD
 ]
 
 
