@@ -185,6 +185,7 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     G.coll = p->kT > 0.0 ? 2 : (p->collision != LB_COLLISION_PROJECTED ? 1 : 0);
     G.seed_lo = uint32_t(p->seed);
     G.seed_hi = uint32_t(p->seed >> 32);
+    G.one = 1.0f;
     P.chunks = G.bchunks;
     Layout& L = P.L;
     size_t o = 0;

@@ -117,6 +117,8 @@ struct Geom {
                           // SMAX_SLOTS slots a cache line apart (tile t updates slot t % SMAX_SLOTS);
                           // NULL: per-tile maxima instead
     int coll;             // 1: general collision (bulk rate, ghost moments kept); 2: with thermal noise
+    float one;            // 1.0: a multiplier the compiler cannot fold, so that the sum of two FP16
+                          // values stays one mixed-precision multiply-add (v_fma_mix)
     unsigned seed_lo, seed_hi;   // key of the noise generator
     long long N;          // nodes per box
     long long rb;         // elements between consecutive rows of one plane (see pop_index)
@@ -156,6 +158,34 @@ __device__ __forceinline__ int row_group_run(int b, int nblocks, int lg)
     if (b >= whole) return b;
     const int k = b >> 3, j = b & 7;
     return ((((k >> lg) << 3) + j) << lg) + (k & ((1 << lg) - 1));
+}
+
+// a = first term or a + x: with the flag a compile-time constant after unrolling, a sum over a
+// fixed set of terms starts at its first term instead of adding it to zero
+template <class T>
+__device__ __forceinline__ void acc_first(T& a, bool& set, T x)
+{
+    a = set ? a + x : x;
+    set = true;
+}
+
+// Post-collision brackets f*_i / w_i of the opposite pair (i, i + 1) from the ten pieces of
+// Eq. fiexp (order of MomPlane): the even part r0 + sum c_ia^2 b_aa + sum c_ia c_ib b_ab is
+// shared, the odd part c_i.a changes sign.
+template <class T>
+__device__ __forceinline__ void rebuild_pair(const T (&p)[MP_N], int i, T& plus, T& minus)
+{
+    const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+    T ev = p[MP_R0], od = 0;
+    bool s_od = false;
+    if (cx != 0) { acc_first(od, s_od, cx > 0 ? p[MP_AX] : -p[MP_AX]); ev += p[MP_BXX]; }
+    if (cy != 0) { acc_first(od, s_od, cy > 0 ? p[MP_AY] : -p[MP_AY]); ev += p[MP_BYY]; }
+    if (cz != 0) { acc_first(od, s_od, cz > 0 ? p[MP_AZ] : -p[MP_AZ]); ev += p[MP_BZZ]; }
+    if (cx * cy != 0) ev += cx * cy > 0 ? p[MP_BXY] : -p[MP_BXY];
+    if (cx * cz != 0) ev += cx * cz > 0 ? p[MP_BXZ] : -p[MP_BXZ];
+    if (cy * cz != 0) ev += cy * cz > 0 ? p[MP_BYZ] : -p[MP_BYZ];
+    plus = ev + od;
+    minus = ev - od;
 }
 
 // One-dimensional weight of a stencil whose first node is `base` at node
@@ -450,8 +480,6 @@ __device__ __forceinline__ void pull_pairs(const _Float16* __restrict__ sb, long
             edge[i] = load_pair<NTL, ADDR>(sb, rb, kp, box_bytes, ny, i, unsigned(sz), unsigned(sy), xe);
         }
     }
-    const bool first = lane == 0;
-    const bool last = lane == 63 || x + 2 == nx;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int cx = cvel(i, 0);
@@ -460,17 +488,16 @@ __device__ __forceinline__ void pull_pairs(const _Float16* __restrict__ sb, long
         } else if (cx > 0) {
             uint32_t prev = edge[i];
             if constexpr (LX >= 64) {
-                // wave_shr:1; lane 0 (no source, bound_ctrl gives 0) takes the edge word below
-                prev = uint32_t(__builtin_amdgcn_mov_dpp(int(own[i]), 0x138, 0xf, 0xf, true));
-                if (first) prev = edge[i];
+                // wave_shr:1; lane 0 has no source lane and, with bound_ctrl off, keeps the edge word
+                prev = uint32_t(__builtin_amdgcn_update_dpp(int(edge[i]), int(own[i]), 0x138, 0xf, 0xf, false));
             }
             w[i] = __builtin_amdgcn_alignbit(own[i], prev, 16);    // (prev.hi, own.lo)
         } else {
             uint32_t next = edge[i];
             if constexpr (LX >= 64) {
-                // wave_shl:1; lane 63 likewise
-                next = uint32_t(__builtin_amdgcn_mov_dpp(int(own[i]), 0x130, 0xf, 0xf, true));
-                if (last) next = edge[i];
+                // wave_shl:1; lane 63 likewise.  In a tile row that runs past nx the lanes past the
+                // end hold x = 0, so the last node pair's right neighbour is the periodic wrap.
+                next = uint32_t(__builtin_amdgcn_update_dpp(int(edge[i]), int(own[i]), 0x130, 0xf, 0xf, false));
             }
             w[i] = __builtin_amdgcn_alignbit(next, own[i], 16);    // (own.hi, next.lo)
         }

@@ -74,9 +74,10 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     const int lx = threadIdx.x % LX, ly = (tid_w / LX) % TY, lz = tid_w / (LX * TY);
     const int x0 = itx * TX + lx * NPL, y0 = ity * TY + ly, z0 = itz * TZ + lz;
     const bool valid = (x0 < G.nx) & (y0 < G.ny) & (z0 < G.nz);
-    // threads past a ragged edge work on a clamped in-range node and contribute nothing
-    // (with two nodes per lane nx is even, so x stays even and x + 1 is in range)
-    const int x = min(x0, G.nx - NPL), y = min(y0, G.ny - 1), z = min(z0, G.nz - 1);
+    // threads past a ragged edge work on an in-range node and contribute nothing: the clamped
+    // one, or with two nodes per lane (nx even) x = 0, the periodic wrap that the lane before
+    // them takes as its right neighbour
+    const int x = NPL == 2 ? (x0 < G.nx ? x0 : 0) : min(x0, G.nx - NPL), y = min(y0, G.ny - 1), z = min(z0, G.nz - 1);
     const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x + 1 == G.nx ? 0 : x + 1;
     const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y + 1 == G.ny ? 0 : y + 1;
     const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z + 1 == G.nz ? 0 : z + 1;
@@ -115,6 +116,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     bool bad = false;
     T mx = 0;                     // FP16: largest |f*_i / w_i| of the lane's nodes
     T uxs[NPL], uys[NPL], uzs[NPL];
+    [[maybe_unused]] T pc[NPL][MP_N];   // two FP16 nodes, projected collision: each node's ten pieces
     const T gcx = T(B.gc[0]), gcy = T(B.gc[1]), gcz = T(B.gc[2]);   // the box's counter-force density
     const T rho0 = T(G.rho0), tau = T(B.tau), om = T(B.omega);         // converted once per lane
 
@@ -122,7 +124,9 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 #pragma unroll
     for (int h = 0; h < NPL; ++h) {
         const int xh = x + h;
-        if constexpr (NPL == 2) {
+        // projected collision on two FP16 nodes per lane: moments straight from the stored halves
+        constexpr bool RAW = NPL == 2 && COLL == 0;
+        if constexpr (NPL == 2 && !RAW) {
             // FP16 value of node xh (low half: x, high half: x + 1), converted exactly, then weighted
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
@@ -132,19 +136,76 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         }
 
         // ---- moments (10 values), over opposite pairs (i, i+1): the pair sum feeds the even
-        // moments (mass, second moments), the difference the odd ones (momentum)
-        T drho = f[0], jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+        // moments (mass, second moments), the difference the odd ones (momentum).  Each sum
+        // starts at its first term (no addition of zero).
+        T drho, jx = 0, jy = 0, jz = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+        if constexpr (RAW) {
+            // Opposite populations share their weight w_i = k_i / 36 (k = 12 rest, 2 axis, 1
+            // diagonal), so each moment is (2^-e / 36) times a sum over pairs of the stored values'
+            // pair sums and differences, the axis pair counted twice.  A pair sum or difference of
+            // two FP16 halves is one mixed-precision multiply-add (by the unit G.one).
+            const T one = T(G.one);
+            auto hv = [&](int i) {
+                const half2_t v = __builtin_bit_cast(half2_t, wpair[i]);
+                return h == 0 ? v.x : v.y;
+            };
+            // per moment: the axis term (at most one per moment but three for the mass) and the
+            // diagonal terms, each accumulated from its first term
+            T ra = 0, rd = 0, xa = 0, xd = 0, ya = 0, yd = 0, za = 0, zd = 0;
+            T qxa = 0, qxd = 0, qya = 0, qyd = 0, qza = 0, qzd = 0;
+            bool s_ra = false, s_rd = false, s_xa = false, s_xd = false, s_ya = false, s_yd = false, s_za = false,
+                 s_zd = false, s_qxa = false, s_qxd = false, s_qya = false, s_qyd = false, s_qza = false,
+                 s_qzd = false, s_pxy = false, s_pxz = false, s_pyz = false;
 #pragma unroll
-        for (int i = 1; i < NQ; i += 2) {
-            const T sm = f[i] + f[i + 1], df = f[i] - f[i + 1];
-            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-            drho += sm;
-            if (cx != 0) { jx += cx > 0 ? df : -df; pxx += sm; }
-            if (cy != 0) { jy += cy > 0 ? df : -df; pyy += sm; }
-            if (cz != 0) { jz += cz > 0 ? df : -df; pzz += sm; }
-            if (cx * cy != 0) pxy += cx * cy > 0 ? sm : -sm;
-            if (cx * cz != 0) pxz += cx * cz > 0 ? sm : -sm;
-            if (cy * cz != 0) pyz += cy * cz > 0 ? sm : -sm;
+            for (int i = 1; i < NQ; i += 2) {
+                const T sm = __builtin_fmaf(float(hv(i)), one, float(hv(i + 1)));
+                const T df = __builtin_fmaf(float(hv(i)), one, -float(hv(i + 1)));
+                const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+                const bool axis = cx * cx + cy * cy + cz * cz == 1;
+                if (axis) acc_first(ra, s_ra, sm); else acc_first(rd, s_rd, sm);
+                if (cx != 0) {
+                    if (axis) { acc_first(xa, s_xa, cx > 0 ? df : -df); acc_first(qxa, s_qxa, sm); }
+                    else { acc_first(xd, s_xd, cx > 0 ? df : -df); acc_first(qxd, s_qxd, sm); }
+                }
+                if (cy != 0) {
+                    if (axis) { acc_first(ya, s_ya, cy > 0 ? df : -df); acc_first(qya, s_qya, sm); }
+                    else { acc_first(yd, s_yd, cy > 0 ? df : -df); acc_first(qyd, s_qyd, sm); }
+                }
+                if (cz != 0) {
+                    if (axis) { acc_first(za, s_za, cz > 0 ? df : -df); acc_first(qza, s_qza, sm); }
+                    else { acc_first(zd, s_zd, cz > 0 ? df : -df); acc_first(qzd, s_qzd, sm); }
+                }
+                if (cx * cy != 0) acc_first(pxy, s_pxy, cx * cy > 0 ? sm : -sm);
+                if (cx * cz != 0) acc_first(pxz, s_pxz, cx * cz > 0 ? sm : -sm);
+                if (cy * cz != 0) acc_first(pyz, s_pyz, cy * cz > 0 ? sm : -sm);
+            }
+            const T u = sc * T(1.0 / 36.0);   // 2^-e / 36: exact enough (one rounding of a constant)
+            drho = u * __builtin_fmaf(float(hv(0)), T(12), __builtin_fmaf(T(2), ra, rd));
+            jx = u * __builtin_fmaf(T(2), xa, xd);
+            jy = u * __builtin_fmaf(T(2), ya, yd);
+            jz = u * __builtin_fmaf(T(2), za, zd);
+            pxx = u * __builtin_fmaf(T(2), qxa, qxd);
+            pyy = u * __builtin_fmaf(T(2), qya, qyd);
+            pzz = u * __builtin_fmaf(T(2), qza, qzd);
+            pxy *= u;
+            pxz *= u;
+            pyz *= u;
+        } else {
+            drho = f[0];
+            bool s_jx = false, s_jy = false, s_jz = false, s_pxx = false, s_pyy = false, s_pzz = false,
+                 s_pxy = false, s_pxz = false, s_pyz = false;
+#pragma unroll
+            for (int i = 1; i < NQ; i += 2) {
+                const T sm = f[i] + f[i + 1], df = f[i] - f[i + 1];
+                const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
+                drho += sm;
+                if (cx != 0) { acc_first(jx, s_jx, cx > 0 ? df : -df); acc_first(pxx, s_pxx, sm); }
+                if (cy != 0) { acc_first(jy, s_jy, cy > 0 ? df : -df); acc_first(pyy, s_pyy, sm); }
+                if (cz != 0) { acc_first(jz, s_jz, cz > 0 ? df : -df); acc_first(pzz, s_pzz, sm); }
+                if (cx * cy != 0) acc_first(pxy, s_pxy, cx * cy > 0 ? sm : -sm);
+                if (cx * cz != 0) acc_first(pxz, s_pxz, cx * cz > 0 ? sm : -sm);
+                if (cy * cz != 0) acc_first(pyz, s_pyz, cy * cz > 0 ? sm : -sm);
+            }
         }
 
         // ---- force density at this node: counter-force + the tile's points
@@ -175,7 +236,9 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             ir = __builtin_amdgcn_rcpf(rho);
         else
             ir = T(1) / rho;
-        const T ux = (jx + T(0.5) * gx) * ir, uy = (jy + T(0.5) * gy) * ir, uz = (jz + T(0.5) * gz) * ir;
+        // rho u = j + g/2 (Eq. macrovariables2)
+        const T hx = jx + T(0.5) * gx, hy = jy + T(0.5) * gy, hz = jz + T(0.5) * gz;
+        const T ux = hx * ir, uy = hy * ir, uz = hz * ir;
 
         if constexpr (MODE == M_MOMENTS) {
             if (valid) {
@@ -253,12 +316,16 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                 br[i] = kg * (f[i] * inv_w - hb);
             }
         }
+        // the equilibrium and forcing part of the stress, rho u_a u_b + tau (u_a g_b + g_a u_b), as
+        // u_b (rho u_a + tau g_a) + u_a tau g_b with rho u_a = h_a
+        const T tgx = tau * gx, tgy = tau * gy, tgz = tau * gz;
+        const T qx = hx + tgx, qy = hy + tgy, qz = hz + tgz;
         T Bxx, Byy, Bzz;
         if constexpr (COLL) {
             // shear drivers of the diagonal; their trace relaxes at omega_b instead (bulk mode)
-            const T dxx = sxx - rho * ux * ux - tau * (T(2) * ux * gx);
-            const T dyy = syy - rho * uy * uy - tau * (T(2) * uy * gy);
-            const T dzz = szz - rho * uz * uz - tau * (T(2) * uz * gz);
+            const T dxx = sxx - ux * (qx + tgx);
+            const T dyy = syy - uy * (qy + tgy);
+            const T dzz = szz - uz * (qz + tgz);
             const T trs = (dxx + dyy + dzz) * third;
             const T tb = T(B.tau_b), omb = T(B.omega_b);
             const T trb = (sxx + syy + szz - rho * (ux * ux + uy * uy + uz * uz) -
@@ -267,13 +334,13 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             Byy = syy - om * (dyy - trs) - omb * trb;
             Bzz = szz - om * (dzz - trs) - omb * trb;
         } else {
-            Bxx = sxx - om * (sxx - rho * ux * ux - tau * (T(2) * ux * gx));
-            Byy = syy - om * (syy - rho * uy * uy - tau * (T(2) * uy * gy));
-            Bzz = szz - om * (szz - rho * uz * uz - tau * (T(2) * uz * gz));
+            Bxx = sxx - om * (sxx - ux * (qx + tgx));
+            Byy = syy - om * (syy - uy * (qy + tgy));
+            Bzz = szz - om * (szz - uz * (qz + tgz));
         }
-        const T Bxy = pxy - om * (pxy - rho * ux * uy - tau * (ux * gy + gx * uy));
-        const T Bxz = pxz - om * (pxz - rho * ux * uz - tau * (ux * gz + gx * uz));
-        const T Byz = pyz - om * (pyz - rho * uy * uz - tau * (uy * gz + gy * uz));
+        const T Bxy = pxy - om * (pxy - (uy * qx + ux * tgy));
+        const T Bxz = pxz - om * (pxz - (uz * qx + ux * tgz));
+        const T Byz = pyz - om * (pyz - (uz * qy + uy * tgz));
         // FP16, two nodes per lane, projected operator: the pieces below carry the output scale 2^e
         // (exact), so the rebuilt brackets are the values to round and each pair of nodes is
         // converted by one packing conversion without a multiply (one node per lane converts
@@ -323,21 +390,21 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             bxz += amp[4];
             byz += amp[5];
         }
+        const T piece[MP_N] = {base, a3x, a3y, a3z, bxx, byy, bzz, bxy, bxz, byz};
+        if constexpr (RAW) {
+            // both nodes' outputs are rebuilt from their pieces after the loop, one packed word at a time
+#pragma unroll
+            for (int k = 0; k < MP_N; ++k) pc[h][k] = piece[k];
+        }
         constexpr bool GHOST = COLL && ST != ST_MOM32;
         // with the ghost part already in br: br + (ev +- od), the same sum as (ev +- od) + br
         br[0] = GHOST ? br[0] + base : base;
 #pragma unroll
         for (int i = 1; i < NQ; i += 2) {
-            const int cx = cvel(i, 0), cy = cvel(i, 1), cz = cvel(i, 2);
-            T ev = base, od = 0;
-            if (cx != 0) { od += cx > 0 ? a3x : -a3x; ev += bxx; }
-            if (cy != 0) { od += cy > 0 ? a3y : -a3y; ev += byy; }
-            if (cz != 0) { od += cz > 0 ? a3z : -a3z; ev += bzz; }
-            if (cx * cy != 0) ev += cx * cy > 0 ? bxy : -bxy;
-            if (cx * cz != 0) ev += cx * cz > 0 ? bxz : -bxz;
-            if (cy * cz != 0) ev += cy * cz > 0 ? byz : -byz;
-            br[i] = GHOST ? br[i] + (ev + od) : ev + od;
-            br[i + 1] = GHOST ? br[i + 1] + (ev - od) : ev - od;
+            T bp, bm;
+            rebuild_pair(piece, i, bp, bm);
+            br[i] = GHOST ? br[i] + bp : bp;
+            br[i + 1] = GHOST ? br[i + 1] + bm : bm;
         }
         if constexpr (COLL == 2 && ST != ST_MOM32) {
             draw(2);
@@ -369,7 +436,8 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         }
 
         // ---- store the post-collision state of this node (two nodes per lane: packed below)
-        if constexpr (NPL == 2) {
+        if constexpr (RAW) {
+        } else if constexpr (NPL == 2) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 if (h == 0)
@@ -397,7 +465,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
 
         // ---- FP16: the largest bracket magnitude (with FOLD already times 2^e), for the range
         // check and the rescaling
-        if constexpr (ST == ST_FP16) {
+        if constexpr (ST == ST_FP16 && !RAW) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) mx = fmax(mx, fabs(br[i]));
         }
@@ -406,7 +474,29 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         uzs[h] = uz;
     }   // nodes of the lane
 
-    if constexpr (NPL == 2) {
+    if constexpr (NPL == 2 && COLL == 0) {
+        // the two nodes' post-collision values (already times 2^e), word by word: rebuilt from the
+        // pieces, packed, folded into the lane's maximum and stored, so that only the pieces stay live
+        if (valid) {
+            auto put = [&](int i, T v0, T v1) {
+                half2_t w;
+                w.x = fp16_out(v0, 1.0f);
+                w.y = fp16_out(v1, 1.0f);
+                mx = fmax(fmax(mx, fabs(v0)), fabs(v1));   // one v_max3
+                store_pair<ADDR>(__builtin_bit_cast(uint32_t, w), reinterpret_cast<_Float16*>(db), G.rb, G.kp,
+                                 box_bytes, G.ny, i, unsigned(z), unsigned(y), x);
+            };
+            put(0, pc[0][MP_R0], pc[1][MP_R0]);
+#pragma unroll
+            for (int i = 1; i < NQ; i += 2) {
+                T p0, m0, p1, m1;
+                rebuild_pair(pc[0], i, p0, m0);
+                rebuild_pair(pc[1], i, p1, m1);
+                put(i, p0, p1);
+                put(i + 1, m0, m1);
+            }
+        }
+    } else if constexpr (NPL == 2) {
         if (valid) {
 #pragma unroll
             for (int i = 0; i < NQ; ++i)
@@ -419,23 +509,25 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
         T m = valid ? mx : T(0);
         bad = bad || ((FOLD ? m : m * B.s_out) > T(65504));
         m = wave_max_nonneg(m);   // m = |f*| magnitudes: non-negative
-        __shared__ float wm[NW];
-        if (lane == 0) wm[wave] = m;
-        __syncthreads();
-        // per-tile maximum; the per-box reduction happens before the next step
-        if (threadIdx.x == 0) {
-            float t = wm[0];
+        // the largest |f*_i / w_i|, without the scale: 1 / 2^e (exact) from the bits of 2^e
+        if (FOLD) m *= __uint_as_float(0x7f000000u - __float_as_uint(B.s_out));
+        if (G.smax) {
+            // one box: each wave into the box's maximum (non-negative floats order as their bit
+            // patterns), no exchange between the block's waves
+            if (lane == 0) atomicMax(G.smax + (tile % SMAX_SLOTS) * SMAX_STRIDE, __float_as_uint(m));
+        } else {
+            // per-tile maximum; the per-box reduction happens before the next step
+            __shared__ float wm[NW];
+            if (lane == 0) wm[wave] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                float t = wm[0];
 #pragma unroll
-            for (int q = 1; q < NW; ++q) t = fmaxf(t, wm[q]);
-            // the largest |f*_i / w_i| of the tile, without the scale (1 / 2^e is exact); one box:
-            // into the box's maximum (non-negative floats order as their bit patterns)
-            t = FOLD ? t * (1.0f / B.s_out) : t;
-            if (G.smax)
-                atomicMax(G.smax + (tile % SMAX_SLOTS) * SMAX_STRIDE, __float_as_uint(t));
-            else
+                for (int q = 1; q < NW; ++q) t = fmaxf(t, wm[q]);
                 ((float*)out1)[tile] = t;
+            }
+            __syncthreads();   // wm is rewritten by the block's next tile
         }
-        __syncthreads();   // wm is rewritten by the block's next tile
     }
     if (__any(bad) && lane == 0) atomicOr(&G.nf[box], 1);
 
@@ -484,7 +576,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
                 o[2] = sz;
             }
         }
-        __syncthreads();   // su is rewritten by the block's next tile
+        if (G.tpb > 1) __syncthreads();   // su is rewritten by the block's next tile
     }
 }
 
