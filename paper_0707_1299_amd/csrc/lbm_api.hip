@@ -376,7 +376,7 @@ void build_points(lb_ctx* c, hipStream_t s)
         blk += prep_blocks(st.n);
     }
     launch_bins(c->p.storage, G, off, c->rec(), c->count(), c->bsum(), c->toff(), c->cursor(), c->tlist(),
-                c->tlist_tmp(), s);
+                c->tlist_tmp(), c->errw(), s);
     c->gc_valid = false;
 }
 
@@ -868,6 +868,10 @@ static int read_flags(lb_ctx* c)
     if (errw[0] & 2) {
         launch_fill_u32(c->errw(), 4, 0u, c->stream);
         return fail(c, LB_ERR_NONFINITE, "non-finite point position or force");
+    }
+    if (errw[0] & 4) {
+        launch_fill_u32(c->errw(), 4, 0u, c->stream);
+        return fail(c, LB_ERR_STATE, "tile-list rebuild: a grid barrier wait ran out (lists may be incomplete)");
     }
     for (int b = 0; b < c->p.nboxes; ++b)
         if (nf[b]) return fail(c, LB_ERR_NONFINITE, "non-finite value or FP16 overflow in box " + std::to_string(b));

@@ -54,7 +54,7 @@ void launch_prep(int storage, const Geom& G, long long n, long long off, const d
                  const int* boxid, void* rec, int* err, double* psum, hipStream_t s);
 long long scan_blocks(long long ntiles);
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
-                 int* cursor, int* tlist, int* tlist_tmp, hipStream_t s);
+                 int* cursor, int* tlist, int* tlist_tmp, int* err, hipStream_t s);
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
                        const double* psum, long long npsum, const float* tmax, double* part, float* pmax,
                        unsigned* ticket, BoxDev* boxes, int zero_net, int fp16_exp, hipStream_t s);

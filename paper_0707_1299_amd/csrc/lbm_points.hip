@@ -144,6 +144,8 @@ __global__ __launch_bounds__(256) void k_prep(const Geom G, long long n, long lo
                                               double* __restrict__ psum)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // the list build's grid-barrier counter (err[2]) starts every build at zero
+    if (i == 0) err[2] = 0;
     double fs[3] = {0.0, 0.0, 0.0};
     if (i < n) prep_point<T>(G, i, off + i, pos, frc, boxid, rec, err, fs);
     if (!psum) return;
@@ -212,23 +214,103 @@ __device__ __forceinline__ void prep_point(const Geom& G, long long i, long long
     }
 }
 
-// 1b. (only when the lists are rebuilt) count the (tile, point) pairs: one group of
-//    gp lanes per point (see lanes_per_point), lane k counting the point in the tile
-//    of slot k.  Windows are chosen afresh (lane 0 stores them) only for the points of
-//    boxes in which a point crossed; the others keep theirs, so what a box computes
-//    never depends on crossings in the other boxes of a batch.
-//    The binning kernels of steps 1b-4 run a capped grid that strides over the work:
-//    in the usual step (no crossing) they only read the flag, and a small grid
-//    does that in little more than the launch.
+// 1b-4. The tile lists, rebuilt in one launch (k_rebin) only while the rebuild flag is set.
+//    In the usual step (no crossing) every block reads the flag and returns: one kernel
+//    boundary per step instead of one per phase.  Otherwise a grid of at most BIN_GRID
+//    blocks (all resident at once: one block of 256 threads per compute unit) runs four
+//    phases separated by grid-wide barriers:
+//      1b count the (tile, point) pairs: one group of gp lanes per point (see
+//         lanes_per_point), lane k counting the point in the tile of slot k.  Windows are
+//         chosen afresh (lane 0 stores them) only for the points of boxes in which a point
+//         crossed; the others keep theirs, so what a box computes never depends on crossings
+//         in the other boxes of a batch;
+//      2  exclusive scan of the per-tile counts into offsets, in chunks of 256 tiles (chunk
+//         sums, then each chunk's prefix and scan; integer sums, so the result does not
+//         depend on the order); count and cursor are cleared for the next build;
+//      3  fill the lists (slot order from atomics), one lane per (point, slot) as in 1b;
+//         the per-box crossing flags are cleared (1b, their only reader, has finished);
+//      4  sort every tile's list by point index, so that sums run in a fixed order: one
+//         thread per entry, its position the number of smaller entries in the same list.
+//    A block passes a barrier only when every block has reached it, so whatever a phase
+//    reads is complete.  The barrier's wait is bounded: a block that waits too long raises
+//    err bit 4 and leaves (the lists then keep a consistent earlier state or miss entries;
+//    the step that reads the flags reports the error).
 constexpr unsigned BIN_GRID = 256;
+constexpr int CHUNK = 256;                 // tiles per scan chunk (threads per block)
+constexpr unsigned BARRIER_SPINS = 1u << 20;
+
+// Grid-wide barrier number k (1, 2, ...) of a launch on the counter bar (zeroed by the
+// records kernel before every launch).  Returns false if the wait ran out.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, int* err)
+{
+    __shared__ int ok;
+    __threadfence();   // this thread's writes, visible to the whole device before the arrival
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        atomicAdd(bar, 1u);
+        const unsigned target = k * gridDim.x;
+        unsigned n = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++n > BARRIER_SPINS) {
+                atomicOr(err, 4);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    __syncthreads();
+    __threadfence();   // later loads see what the other blocks wrote before arriving
+    return ok != 0;
+}
+
+// Sum of v over the 256 threads of the block, returned to every thread (fixed order).
+__device__ __forceinline__ int block_sum_256(int v, int* sh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    const int t = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive scan of v over the 256 threads of the block; total to every thread.
+__device__ __forceinline__ int block_exclusive_scan_256(int v, int* sh, int& total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    int pre = 0;
+    for (int w = 0; w < wave; ++w) pre += sh[w];
+    total = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return pre + incl - v;
+}
 
 template <class T>
-__global__ __launch_bounds__(256) void k_count(const Geom G, long long n, int gp, const PRec<T>* __restrict__ rec,
-                                               int* __restrict__ count)
+__global__ __launch_bounds__(256) void k_rebin(const Geom G, long long npts, int gp, const PRec<T>* __restrict__ rec,
+                                               int* __restrict__ count, int* __restrict__ bsum, int* __restrict__ toff,
+                                               int* __restrict__ cursor, int* __restrict__ tlist_tmp,
+                                               int* __restrict__ tlist, long long max_entries, int* __restrict__ err)
 {
     if (!*G.rebin) return;
-    const long long total = n * gp, stride = (long long)gridDim.x * blockDim.x;
-    for (long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x; gid < total; gid += stride) {
+    __shared__ int sh[4];
+    unsigned* bar = reinterpret_cast<unsigned*>(err + 2);
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long gid0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+
+    // 1b. count
+    for (long long gid = gid0; gid < npts * gp; gid += stride) {
         const long long p = gid / gp;
         const int k = int(gid % gp);
         if (k >= G.maxp) continue;
@@ -243,77 +325,24 @@ __global__ __launch_bounds__(256) void k_count(const Geom G, long long n, int gp
         const long long t = slot_tile(G, s, r.box, k);
         if (t >= 0) atomicAdd(&count[t], 1);
     }
-}
+    if (!grid_barrier(bar, 1, err)) return;
 
-// ---------------------------------------------------------------------------
-// 2. exclusive scan of the per-tile counts into offsets (two passes; integer
-//    sums, so the result does not depend on the order).  The second pass also
-//    clears count and cursor for the next build.
-constexpr int SCAN_B = 1024;
-
-__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total)
-{
-    // 1024 threads: wave-level inclusive scan, then scan of the 16 wave totals
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += u;
-    }
-    if (lane == 63) sh[wave] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int w = 0; w < SCAN_B / 64; ++w) {
-            const int t = sh[w];
-            sh[w] = acc;
-            acc += t;
-        }
-        sh[SCAN_B / 64] = acc;
-    }
-    __syncthreads();
-    total = sh[SCAN_B / 64];
-    const int r = sh[wave] + incl - v;
-    __syncthreads();
-    return r;
-}
-
-// Chunks of SCAN_B counts; block b of the (capped) grid takes chunks b, b + grid, ...
-constexpr unsigned SCAN_GRID = 16;
-
-__global__ __launch_bounds__(SCAN_B) void k_scan_sums(long long n, const int* __restrict__ count, int* __restrict__ bsum,
-                                                      const int* __restrict__ rebin)
-{
-    if (!*rebin) return;
-    __shared__ int sh[SCAN_B / 64 + 1];
-    const long long nch = (n + SCAN_B - 1) / SCAN_B;
+    // 2. scan: chunk sums, then each chunk's prefix and exclusive scan
+    const long long n = G.ntiles, nch = (n + CHUNK - 1) / CHUNK;
     for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
-        const long long i = c * SCAN_B + threadIdx.x;
+        const long long i = c * CHUNK + threadIdx.x;
+        const int t = block_sum_256(i < n ? count[i] : 0, sh);
+        if (threadIdx.x == 0) bsum[c] = t;
+    }
+    if (!grid_barrier(bar, 2, err)) return;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        int acc = 0;
+        for (long long q = threadIdx.x; q < c; q += CHUNK) acc += bsum[q];
+        const int pre = block_sum_256(acc, sh);
+        const long long i = c * CHUNK + threadIdx.x;
         const int v = i < n ? count[i] : 0;
         int total;
-        block_exclusive_scan(v, sh, total);
-        if (threadIdx.x == 0) bsum[c] = total;
-    }
-}
-
-__global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restrict__ count, const int* __restrict__ bsum,
-                                                       int* __restrict__ toff, int* __restrict__ cursor,
-                                                       const int* __restrict__ rebin)
-{
-    if (!*rebin) return;
-    __shared__ int sh[SCAN_B / 64 + 1];
-    const long long nch = (n + SCAN_B - 1) / SCAN_B;
-    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
-        // prefix of the chunk sums before this chunk
-        int acc = 0;
-        for (long long b = threadIdx.x; b < c; b += SCAN_B) acc += bsum[b];
-        int pre;
-        block_exclusive_scan(acc, sh, pre);
-        const long long i = c * SCAN_B + threadIdx.x;
-        const int v = i < n ? count[i] : 0;
-        int total;
-        const int ex = block_exclusive_scan(v, sh, total);
+        const int ex = block_exclusive_scan_256(v, sh, total);
         if (i < n) {
             toff[i] = pre + ex;
             count[i] = 0;
@@ -321,18 +350,9 @@ __global__ __launch_bounds__(SCAN_B) void k_scan_write(long long n, int* __restr
         }
         if (c == nch - 1 && threadIdx.x == 0) toff[n] = pre + total;
     }
-}
+    if (!grid_barrier(bar, 3, err)) return;
 
-// ---------------------------------------------------------------------------
-// 3. fill the per-tile point lists (slot order from atomics; fixed by step 4),
-//    one lane per (point, slot) as in step 1b.  Also clears the per-box crossing
-//    flags (step 1b, their only reader, has finished).
-__global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int gp, const int* __restrict__ toff,
-                                              int* __restrict__ cursor, int* __restrict__ tlist)
-{
-    if (!*G.rebin) return;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long gid0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // 3. fill
     for (long long b = gid0; b < G.nboxes; b += stride) G.rebox[b] = 0;
     for (long long gid = gid0; gid < npts * gp; gid += stride) {
         const long long p = gid / gp;
@@ -349,21 +369,14 @@ __global__ __launch_bounds__(256) void k_fill(const Geom G, long long npts, int 
         if (cz >= G.nz) cz -= G.nz;
         const bool home = t == tile_id(G, w.w, cz >> G.ltz, cy >> G.lty, cx >> G.ltx);
         const int slot = toff[t] + atomicAdd(&cursor[t], 1);
-        tlist[slot] = int(p << PK_SHIFT) | (home ? PK_HOME : 0) | k;
+        tlist_tmp[slot] = int(p << PK_SHIFT) | (home ? PK_HOME : 0) | k;
     }
-}
+    if (!grid_barrier(bar, 4, err)) return;
 
-// 4. sort every tile's list by point index (so sums run in a fixed order).  One
-//    thread per list entry: its position is the number of smaller entries in the
-//    same list (entries are distinct), found by a scan of that list; empty tiles
-//    cost nothing.
-__global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_entries, const int* __restrict__ toff,
-                                                    const int* __restrict__ tin, int* __restrict__ tout)
-{
-    if (!*G.rebin) return;
-    const long long n = min(max_entries, (long long)toff[G.ntiles]);
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        const int v = tin[e];
+    // 4. sort
+    const long long ne = min(max_entries, (long long)toff[G.ntiles]);
+    for (long long e = gid0; e < ne; e += stride) {
+        const int v = tlist_tmp[e];
         const int p = pk_point(v), k = pk_slot(v);
         const int4 w = G.win[p];
         TileSet s;
@@ -371,8 +384,8 @@ __global__ __launch_bounds__(256) void k_sort_slots(const Geom G, long long max_
         const long long t = slot_tile(G, s, w.w, k);
         const int a = toff[t], b = toff[t + 1];
         int rank = 0;
-        for (int j = a; j < b; ++j) rank += tin[j] < v ? 1 : 0;
-        tout[a + rank] = v;
+        for (int j = a; j < b; ++j) rank += tlist_tmp[j] < v ? 1 : 0;
+        tlist[a + rank] = v;
     }
 }
 
@@ -870,33 +883,22 @@ void launch_prep(int storage, const Geom& G, long long n, long long off, const d
                            (PRec<float>*)rec, err, psum);
 }
 
-long long scan_blocks(long long ntiles) { return (ntiles + SCAN_B - 1) / SCAN_B; }
+long long scan_blocks(long long ntiles) { return (ntiles + CHUNK - 1) / CHUNK; }
 
 // Steps 1b-4 over all npts points, after the records of every set are written
-// (any set may raise the rebuild flag).
+// (any set may raise the rebuild flag; the records kernel zeroed the barrier counter).
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
-                 int* cursor, int* tlist, int* tlist_tmp, hipStream_t s)
+                 int* cursor, int* tlist, int* tlist_tmp, int* err, hipStream_t s)
 {
-    const int gp = lanes_per_point(G.maxp);
-    const unsigned gb = std::min<unsigned>(BIN_GRID, nblk(std::max(npts * gp, 1LL), 256));
-    if (npts > 0) {
-        if (storage == ST_FP64)
-            hipLaunchKernelGGL(k_count<double>, dim3(gb), dim3(256), 0, s, G, npts, gp, (const PRec<double>*)rec,
-                               count);
-        else
-            hipLaunchKernelGGL(k_count<float>, dim3(gb), dim3(256), 0, s, G, npts, gp, (const PRec<float>*)rec,
-                               count);
-    }
-    const unsigned nb = (unsigned)std::min<long long>(SCAN_GRID, scan_blocks(G.ntiles));
-    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, (const int*)count, bsum,
-                       (const int*)G.rebin);
-    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(SCAN_B), 0, s, G.ntiles, count, (const int*)bsum, toff, cursor,
-                       (const int*)G.rebin);
     if (npts <= 0) return;
+    const int gp = lanes_per_point(G.maxp);
     const long long max_entries = npts * G.maxp;
-    hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, s, G, npts, gp, (const int*)toff, cursor, tlist_tmp);
-    hipLaunchKernelGGL(k_sort_slots, dim3(std::min<unsigned>(BIN_GRID, nblk(max_entries, 256))), dim3(256), 0, s, G,
-                       max_entries, (const int*)toff, (const int*)tlist_tmp, tlist);
+    if (storage == ST_FP64)
+        hipLaunchKernelGGL(k_rebin<double>, dim3(BIN_GRID), dim3(256), 0, s, G, npts, gp, (const PRec<double>*)rec,
+                           count, bsum, toff, cursor, tlist_tmp, tlist, max_entries, err);
+    else
+        hipLaunchKernelGGL(k_rebin<float>, dim3(BIN_GRID), dim3(256), 0, s, G, npts, gp, (const PRec<float>*)rec,
+                           count, bsum, toff, cursor, tlist_tmp, tlist, max_entries, err);
 }
 
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
