@@ -95,8 +95,9 @@ typedef struct lb_params {
     int32_t tile_x;         /* tile shape (nodes); 0 = default. tile_x*tile_y*tile_z = 256 */
     int32_t tile_y;
     int32_t tile_z;
-    int32_t fp16_exponent;  /* FP16 only: initial scale exponent; 0 = default (30, or from
-                               the thermal amplitude when kT > 0) */
+    int32_t fp16_exponent;  /* FP16 only: initial scale exponent in [-100, 120] (the range the
+                               exponent is kept in from step to step); 0 = default (30, or
+                               from the thermal amplitude when kT > 0) */
     int32_t variant;        /* step-kernel variant bits (same results, different memory access):
                                1 = 64-bit per-lane addresses instead of scalar
                                    descriptors plus 32-bit lane offsets,

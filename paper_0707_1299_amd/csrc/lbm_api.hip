@@ -118,6 +118,10 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
         return LB_ERR_ARG;
     }
     if (!(p->kT >= 0.0) || !isfinite(p->kT)) { why = "kT must be finite and >= 0"; return LB_ERR_ARG; }
+    if (p->fp16_exponent < -100 || p->fp16_exponent > 120) {
+        why = "fp16_exponent must lie in [-100, 120] (the range the scale exponent is kept in)";
+        return LB_ERR_ARG;
+    }
     if (p->storage == LB_STORAGE_MOM32 && p->kT > 0.0) {
         why = "moment storage keeps no ghost moments: thermal noise needs population storage";
         return LB_ERR_ARG;

@@ -59,6 +59,7 @@ def test_workspace_bytes_pure_and_monotone():
     dict(collision="mrt", ghost_rate=0.0), dict(collision="mrt", ghost_rate=4.5),
     dict(storage="mom32", collision="bgk"), dict(storage="mom32", collision="mrt", ghost_rate=1.5),
     dict(kT=-1e-5), dict(kT=float("inf")), dict(storage="mom32", kT=1e-5),
+    dict(storage="fp16", fp16_exponent=121), dict(storage="fp16", fp16_exponent=-101),
     # boxes of 4 GiB or more need at least 64 lanes along x (box-relative offsets are 32-bit)
     dict(shape=(512, 512, 512), storage="fp32", tile=(32, 4, 2)),
     dict(shape=(512, 512, 512), storage="fp16", tile=(64, 2, 2)),     # two nodes per lane: 32 lanes
