@@ -244,9 +244,10 @@ constexpr unsigned BARRIER_SPINS = 1u << 20;
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, int* err)
 {
     __shared__ int ok;
-    __threadfence();   // this thread's writes, visible to the whole device before the arrival
-    __syncthreads();
+    __syncthreads();   // the block's writes have reached the compute unit's L2 (L1 writes through)
     if (threadIdx.x == 0) {
+        // one device-scope release per block: the write-back covers every wave's writes in L2
+        __threadfence();
         ok = 1;
         atomicAdd(bar, 1u);
         const unsigned target = k * gridDim.x;
@@ -259,9 +260,10 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, int* err
             }
             __builtin_amdgcn_s_sleep(8);
         }
+        // acquire for the block: the invalidation of L1 and L2 serves every wave's later loads
+        __threadfence();
     }
     __syncthreads();
-    __threadfence();   // later loads see what the other blocks wrote before arriving
     return ok != 0;
 }
 
