@@ -216,9 +216,9 @@ __device__ __forceinline__ void prep_point(const Geom& G, long long i, long long
 
 // 1b-4. The tile lists, rebuilt in one launch (k_rebin) only while the rebuild flag is set.
 //    In the usual step (no crossing) every block reads the flag and returns: one kernel
-//    boundary per step instead of one per phase.  Otherwise a grid of at most BIN_GRID
-//    blocks (all resident at once: one block of 256 threads per compute unit) runs four
-//    phases separated by grid-wide barriers:
+//    boundary per step instead of one per phase.  Otherwise a grid of one block of 256
+//    threads per compute unit (at most BIN_GRID; all resident at once) runs four phases
+//    separated by grid-wide barriers:
 //      1b count the (tile, point) pairs: one group of gp lanes per point (see
 //         lanes_per_point), lane k counting the point in the tile of slot k.  Windows are
 //         chosen afresh (lane 0 stores them) only for the points of boxes in which a point
@@ -887,6 +887,17 @@ void launch_prep(int storage, const Geom& G, long long n, long long off, const d
 
 long long scan_blocks(long long ntiles) { return (ntiles + CHUNK - 1) / CHUNK; }
 
+// Blocks of the list build: one per compute unit of the current device, at most BIN_GRID,
+// so that the grid is resident at once even on a partition of the GPU.
+static unsigned rebin_grid()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 32;
+    return std::min<unsigned>(BIN_GRID, unsigned(cus));
+}
+
 // Steps 1b-4 over all npts points, after the records of every set are written
 // (any set may raise the rebuild flag; the records kernel zeroed the barrier counter).
 void launch_bins(int storage, const Geom& G, long long npts, const void* rec, int* count, int* bsum, int* toff,
@@ -895,12 +906,13 @@ void launch_bins(int storage, const Geom& G, long long npts, const void* rec, in
     if (npts <= 0) return;
     const int gp = lanes_per_point(G.maxp);
     const long long max_entries = npts * G.maxp;
+    const unsigned nb = rebin_grid();
     if (storage == ST_FP64)
-        hipLaunchKernelGGL(k_rebin<double>, dim3(BIN_GRID), dim3(256), 0, s, G, npts, gp, (const PRec<double>*)rec,
-                           count, bsum, toff, cursor, tlist_tmp, tlist, max_entries, err);
+        hipLaunchKernelGGL(k_rebin<double>, dim3(nb), dim3(256), 0, s, G, npts, gp, (const PRec<double>*)rec, count,
+                           bsum, toff, cursor, tlist_tmp, tlist, max_entries, err);
     else
-        hipLaunchKernelGGL(k_rebin<float>, dim3(BIN_GRID), dim3(256), 0, s, G, npts, gp, (const PRec<float>*)rec,
-                           count, bsum, toff, cursor, tlist_tmp, tlist, max_entries, err);
+        hipLaunchKernelGGL(k_rebin<float>, dim3(nb), dim3(256), 0, s, G, npts, gp, (const PRec<float>*)rec, count,
+                           bsum, toff, cursor, tlist_tmp, tlist, max_entries, err);
 }
 
 void launch_box_update(int storage, const Geom& G, const void* rec, const int* toff, const int* tlist,
