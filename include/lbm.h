@@ -266,7 +266,11 @@ int lb_clear_forces(lb_ctx* ctx);
  * after Eq. halftransform), then advance colloids by the Sec. IV update
  * (explicit Euler).  Repeated chunks of 2, 4, ..., 128 steps run as captured
  * HIP graphs (captured on first use per chunk length, parity and set of
- * registered forces).
+ * registered forces).  Returns after enqueueing.  Conditions the kernels flag
+ * (LB_ERR_NONFINITE for a non-finite value or FP16 overflow, LB_ERR_ARG for a
+ * box id out of range, LB_ERR_STATE when a tile-list rebuild's device-wide
+ * barrier wait ran out) are reported by the next call that reads the flags
+ * (lb_sync, lb_diagnostics).
  */
 int lb_step(lb_ctx* ctx, int32_t nsteps);
 
