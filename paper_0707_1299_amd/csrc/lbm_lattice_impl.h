@@ -580,18 +580,32 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
     }
 }
 
+// Waves per SIMD the step kernel asks the compiler for (its register budget), where the
+// default allocation would round up past a granule and lose a wave:
+// - two FP16 nodes per lane, projected collision: this step waits mostly on memory and pays for
+//   more waves than the 5 the compiler's 84 VGPRs allow unbounded: 7 (72 VGPRs, a few scalar
+//   registers spilled to VGPR lanes) where a wave covers a tile row, 6 (80 VGPRs) for narrower
+//   rows, whose per-lane neighbour loads need more registers;
+// - one node per lane on tile rows of at least 64 nodes, FP32 arithmetic: the general collision
+//   (7 waves, 72 VGPRs) and the thermal step (5 waves, 96 VGPRs), which would take 73-75 and
+//   98-99 VGPRs unbounded.
+// Only the two-node kernels on 128 x 1 x 2 and 256 x 1 x 1 tiles spill (one VGPR); the other
+// forms (narrower rows, 64-bit addressing, FP64) would spill more and keep the default.
+constexpr int step_waves(int ST, int TX, int NPL, int VAR, int COLL)
+{
+    if (VAR & 1) return 1;
+    if (NPL == 2) return COLL == 0 ? (TX / NPL >= 64 ? 7 : 6) : 1;
+    if ((ST == ST_FP32 || ST == ST_FP16) && TX >= 64) return COLL == 1 ? 7 : (COLL == 2 ? 5 : 1);
+    return 1;
+}
+
 // One block per run of G.tpb consecutive tiles, in the block order G.order names
 // (launch order, contiguous runs per XCD, or tile rows kept on one XCD); each tile is
 // finished before the next.  BLOCK / NPL threads per block.
 // With COLL == 2 the block of tile 0 also advances the step counter for the next
 // step (*tout = *tin + 1; the two slots alternate with the population copies).
-// Two FP16 nodes per lane, projected collision, buffer addressing: this step waits mostly on
-// memory, so it asks for more waves per SIMD than the 5 the compiler's 84 VGPRs allow
-// unbounded: 7 (72 VGPRs, a few scalar registers spilled to VGPR lanes) where a wave covers a
-// tile row, 6 (80 VGPRs) for narrower rows, whose per-lane neighbour loads need more
-// registers.  Neither spills VGPRs; the other forms would under such bounds.
 template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1>
-__global__ __launch_bounds__(BLOCK / NPL, NPL == 2 && COLL == 0 && !(VAR & 1) ? (TX / NPL >= 64 ? 7 : 6) : 1)
+__global__ __launch_bounds__(BLOCK / NPL, MODE == M_STEP ? step_waves(ST, TX, NPL, VAR, COLL) : 1)
 void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
                                                    const BoxDev* __restrict__ boxes, const int* __restrict__ toff,
