@@ -114,7 +114,11 @@ typedef struct lb_params {
                                    same y, z tile index) run back to back on one
                                    XCD, tile rows in launch order across the XCDs
                                    (overrides 16; where the blocks per tile row are
-                                   not a power of two, launch order).
+                                   not a power of two, launch order),
+                               128 = with one tile per block (4 * k = 0), a step
+                                   kernel compiled for exactly one tile per block,
+                                   without the tile loop: fewer scalar registers
+                                   held and spilled (valid only with k = 0).
                                With LB_STORAGE_MOM32 bits 0 and 1 have no effect: each
                                node gathers the pieces of its 18 neighbours with cached
                                buffer loads. */

@@ -19,6 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblbm.so")
 SOURCES = ["lbm_lattice_fp64.hip", "lbm_lattice_fp32.hip", "lbm_lattice_fp16.hip", "lbm_lattice_mom32.hip",
+           "lbm_lattice_fp64_one.hip", "lbm_lattice_fp32_one.hip", "lbm_lattice_fp16_one.hip", "lbm_lattice_mom32_one.hip",
            "lbm_lattice.hip", "lbm_points.hip", "lbm_elastic.hip", "lbm_api.hip", "lbm_mlp.hip", "lbm_probe.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 

@@ -103,7 +103,8 @@ int make_plan(const lb_params* p, Plan& P, std::string& why)
     if (p->storage < LB_STORAGE_FP64 || p->storage > LB_STORAGE_MOM32) { why = "unknown storage"; return LB_ERR_ARG; }
     if (p->max_points < 0) { why = "max_points must be >= 0"; return LB_ERR_ARG; }
     if (!(p->rho0 >= 0.0) || !isfinite(p->rho0)) { why = "rho0 must be finite and >= 0"; return LB_ERR_ARG; }
-    if (p->variant < 0 || p->variant > 127) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if (p->variant < 0 || p->variant > 255) { why = "unknown kernel variant"; return LB_ERR_ARG; }
+    if ((p->variant & 128) && ((p->variant >> 2) & 3)) { why = "variant 128 needs one tile per block"; return LB_ERR_ARG; }
     if (p->collision < LB_COLLISION_PROJECTED || p->collision > LB_COLLISION_MRT) {
         why = "unknown collision operator";
         return LB_ERR_ARG;

@@ -368,7 +368,7 @@ __device__ __forceinline__ void lattice_tile(const Geom& G, const int tile,
             T r[4];
             box_muller<T>(q.v[0], q.v[1], r[0], r[1]);
             box_muller<T>(q.v[2], q.v[3], r[2], r[3]);
-            const T sr = sqrt(rho);
+            const T sr = noise_sqrt(rho);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int k = 4 * j + m;
@@ -601,10 +601,15 @@ constexpr int step_waves(int ST, int TX, int NPL, int VAR, int COLL)
 
 // One block per run of G.tpb consecutive tiles, in the block order G.order names
 // (launch order, contiguous runs per XCD, or tile rows kept on one XCD); each tile is
-// finished before the next.  BLOCK / NPL threads per block.
+// finished before the next.  BLOCK / NPL threads per block.  ONE (variant bit 128,
+// with G.tpb == 1): the kernel is compiled for exactly one tile per block.  Without the
+// tile loop the compiler has no loop to hoist the tile's wave-uniform values out of,
+// values it otherwise keeps in scalar registers across the loop and spills into VGPR
+// lanes (the thermal step: 47 such spills and 1111 VALU instructions with the loop,
+// none and 864 without).  Both forms compute the same values bit for bit.
 // With COLL == 2 the block of tile 0 also advances the step counter for the next
 // step (*tout = *tin + 1; the two slots alternate with the population copies).
-template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1>
+template <int ST, int TX, int TY, int TZ, int MODE, int VAR, int COLL = 0, int NPL = 1, bool ONE = false>
 __global__ __launch_bounds__(BLOCK / NPL, MODE == M_STEP ? step_waves(ST, TX, NPL, VAR, COLL) : 1)
 void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
                                                    typename StoreT<ST>::S* __restrict__ dst,
@@ -617,9 +622,16 @@ void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
 {
     const int b = int(blockIdx.x), nb = int(gridDim.x);
     const int first = (G.order == 1 ? b : G.order == 0 ? xcd_tile(b, nb) : row_group_run(b, nb, G.lgrp)) * G.tpb;
-    const int last = min((long long)first + G.tpb, G.ntiles);
-    for (int tile = first; tile < last; ++tile)
-        lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL, NPL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1, tin);
+    if constexpr (ONE) {
+        if (first < G.ntiles)
+            lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL, NPL>(G, first, src, dst, boxes, toff, tlist, rec, out0, out1,
+                                                               tin);
+    } else {
+        const int last = min((long long)first + G.tpb, G.ntiles);
+        for (int tile = first; tile < last; ++tile)
+            lattice_tile<ST, TX, TY, TZ, MODE, VAR, COLL, NPL>(G, tile, src, dst, boxes, toff, tlist, rec, out0, out1,
+                                                               tin);
+    }
     if constexpr (COLL == 2)
         if (first == 0 && threadIdx.x == 0) *tout = *tin + 1;
     // the tile lists of this step were current; the next step's records raise the flag again
@@ -634,7 +646,7 @@ void k_lattice(const Geom G, const typename StoreT<ST>::S* __restrict__ src,
 
 // With ev0/ev1 set, the runtime stamps the two events at the kernel's own start
 // and end (timing without the dispatch latency of separate event records).
-template <int ST, int TX, int TY, int TZ, int VAR, int COLL>
+template <int ST, int TX, int TY, int TZ, int VAR, int COLL, bool ONE>
 static void launch_step_c(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
                           const void* rec, double* out0, double* out1, const unsigned long long* tin,
                           unsigned long long* tout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
@@ -646,42 +658,42 @@ static void launch_step_c(const Geom& G, const void* src, void* dst, BoxDev* box
         if (G.pairs) {
             // two nodes per lane
             if (ev0 && ev1)
-                hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 2>), dim3(nb), dim3(BLOCK / 2), 0,
+                hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 2, ONE>), dim3(nb), dim3(BLOCK / 2), 0,
                                       s, ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist,
                                       (const PRec<T>*)rec, out0, out1, tin, tout);
             else
-                hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 2>), dim3(nb), dim3(BLOCK / 2), 0, s,
+                hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 2, ONE>), dim3(nb), dim3(BLOCK / 2), 0, s,
                                    G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1, tin,
                                    tout);
             return;
         }
     }
     if (ev0 && ev1)
-        hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s,
+        hipExtLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 1, ONE>), dim3(nb), dim3(BLOCK), 0, s,
                               ev0, ev1, 0, G, (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0,
                               out1, tin, tout);
     else
-        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL>), dim3(nb), dim3(BLOCK), 0, s, G,
+        hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_STEP, VAR, COLL, 1, ONE>), dim3(nb), dim3(BLOCK), 0, s, G,
                            (const S*)src, (S*)dst, boxes, toff, tlist, (const PRec<T>*)rec, out0, out1, tin, tout);
 }
 
-template <int ST, int TX, int TY, int TZ, int VAR>
+template <int ST, int TX, int TY, int TZ, int VAR, bool ONE>
 static void launch_step_v(const Geom& G, const void* src, void* dst, BoxDev* boxes, const int* toff, const int* tlist,
                           const void* rec, double* out0, double* out1, const unsigned long long* tin,
                           unsigned long long* tout, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     // the general and thermal operators are instantiated with buffer addressing only (bit 0 off)
     if (G.coll == 2)
-        launch_step_c<ST, TX, TY, TZ, VAR & ~1, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
+        launch_step_c<ST, TX, TY, TZ, VAR & ~1, 2, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
                                                    ev1);
     else if (G.coll == 1)
-        launch_step_c<ST, TX, TY, TZ, VAR & ~1, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
+        launch_step_c<ST, TX, TY, TZ, VAR & ~1, 1, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0,
                                                    ev1);
     else
-        launch_step_c<ST, TX, TY, TZ, VAR, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1);
+        launch_step_c<ST, TX, TY, TZ, VAR, 0, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1);
 }
 
-template <int ST, int TX, int TY, int TZ>
+template <int ST, int TX, int TY, int TZ, bool ONE>
 static void launch_lattice_t(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
                              const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
                              const unsigned long long* tin, unsigned long long* tout, hipStream_t s, hipEvent_t ev0,
@@ -695,11 +707,13 @@ static void launch_lattice_t(const Geom& G, int mode, int variant, const void* s
     auto r = (const PRec<T>*)rec;
     if (mode == M_STEP) {
         switch (variant & 3) {
-        case 1: launch_step_v<ST, TX, TY, TZ, 1>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
-        case 2: launch_step_v<ST, TX, TY, TZ, 2>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
-        case 3: launch_step_v<ST, TX, TY, TZ, 3>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
-        default: launch_step_v<ST, TX, TY, TZ, 0>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
+        case 1: launch_step_v<ST, TX, TY, TZ, 1, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
+        case 2: launch_step_v<ST, TX, TY, TZ, 2, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
+        case 3: launch_step_v<ST, TX, TY, TZ, 3, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
+        default: launch_step_v<ST, TX, TY, TZ, 0, ONE>(G, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, ev0, ev1); break;
         }
+    } else if constexpr (ONE) {
+        // the one-tile instantiations are step kernels only
     } else if (mode == M_MOMENTS) {
         hipLaunchKernelGGL((k_lattice<ST, TX, TY, TZ, M_MOMENTS, 0>), dim3(nblocks), dim3(BLOCK), 0, s, G, a0, a1,
                            boxes, toff, tlist, r, out0, out1, nullptr, nullptr);
@@ -709,7 +723,7 @@ static void launch_lattice_t(const Geom& G, int mode, int variant, const void* s
     }
 }
 
-template <int ST>
+template <int ST, bool ONE>
 static bool launch_lattice_s(const Geom& G, int mode, int variant, const void* src, void* dst, BoxDev* boxes,
                              const int* toff, const int* tlist, const void* rec, double* out0, double* out1,
                              const unsigned long long* tin, unsigned long long* tout, hipStream_t s, hipEvent_t ev0,
@@ -717,7 +731,7 @@ static bool launch_lattice_s(const Geom& G, int mode, int variant, const void* s
 {
 #define LBM_TILE(X, Y, Z)                                                                                     \
     if (G.tx == X && G.ty == Y && G.tz == Z) {                                                                \
-        launch_lattice_t<ST, X, Y, Z>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, \
+        launch_lattice_t<ST, X, Y, Z, ONE>(G, mode, variant, src, dst, boxes, toff, tlist, rec, out0, out1, tin, tout, s, \
                                       ev0, ev1);                                                              \
         return true;                                                                                          \
     }

@@ -23,6 +23,8 @@ ARCH = "gfx950"
 TILES = [(64, 2, 2), (64, 4, 1), (64, 1, 4), (128, 2, 1), (128, 1, 2), (256, 1, 1), (32, 4, 2), (32, 2, 4),
          (16, 4, 4)]
 VARIANTS = [0, 2, 4, 6, 8, 10, 16, 18, 20, 22, 66, 70]
+# the one-tile-per-block variants also in the step kernel built without the tile loop (bit 128)
+VARIANTS += [v | 128 for v in VARIANTS if not (v >> 2) & 3]
 
 
 def key(shape, storage, nboxes, tag=None):

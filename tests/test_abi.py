@@ -54,7 +54,7 @@ def test_workspace_bytes_pure_and_monotone():
 
 @pytest.mark.parametrize("kw", [
     dict(shape=(3, 32, 32)), dict(shape=(32, 32, 2)), dict(nboxes=0), dict(storage=7),
-    dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=128), dict(variant=-1),
+    dict(max_points=-1), dict(tile=(64, 3, 1)), dict(variant=256), dict(variant=-1), dict(variant=132),
     dict(storage="mom32", tile=(16, 8, 2)), dict(collision=3), dict(collision=-1),
     dict(collision="mrt", ghost_rate=0.0), dict(collision="mrt", ghost_rate=4.5),
     dict(storage="mom32", collision="bgk"), dict(storage="mom32", collision="mrt", ghost_rate=1.5),

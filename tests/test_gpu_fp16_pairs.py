@@ -68,6 +68,8 @@ CASES = [
     ((11, 6, 256), (64, 2, 2), 66),     # the two tiles of a tile row on one XCD, 33 tile rows
     ((9, 7, 512), (128, 2, 1), 82),     # 4 tiles per tile row on one XCD, 36 rows (4 past the last group of 8)
     ((10, 8, 512), (128, 2, 1), 86),    # 2 runs of 2 tiles per tile row on one XCD
+    ((13, 10, 70), (128, 2, 1), 128),   # the step kernel without the tile loop, ragged wave
+    ((9, 7, 512), (128, 2, 1), 194),    # the same, tile rows on one XCD
 ]
 
 

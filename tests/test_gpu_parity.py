@@ -309,7 +309,7 @@ def test_kernel_variants_bitwise_equal(storage):
     ref = None
     t0 = (64, 2, 2)
     cases = ((t0, 0), (t0, 1), (t0, 2), (t0, 3), (t0, 4), (t0, 10), (t0, 12), (t0, 16), (t0, 22), (t0, 66),
-             (t0, 70), ((128, 2, 1), 1), ((128, 2, 1), 16))
+             (t0, 70), (t0, 128), (t0, 130), (t0, 194), ((128, 2, 1), 1), ((128, 2, 1), 16), ((128, 2, 1), 144))
     for tile, variant in cases:
         _, u, o = run_gpu((L, L, L), storage, 0.5, sets, 12, tile=tile, variant=variant)
         if ref is None:

@@ -112,7 +112,9 @@ def test_thermal_run_independent_of_graphs_tiles_and_variants():
     u0, o0 = gpu_run(shape, "fp32", 0.6, 1e-5, 41, sets)                                        # graphs + tail
     u1, o1 = gpu_run(shape, "fp32", 0.6, 1e-5, 41, sets, step_chunks=[3] * 13 + [2])            # other split
     u2, o2 = gpu_run(shape, "fp32", 0.6, 1e-5, 41, sets, tile=(32, 4, 2), variant=6)
-    assert np.array_equal(u0, u1) and np.array_equal(u0, u2)
+    u3, o3 = gpu_run(shape, "fp32", 0.6, 1e-5, 41, sets, variant=128)                          # no tile loop
+    assert np.array_equal(u0, u1) and np.array_equal(u0, u2) and np.array_equal(u0, u3)
+    assert np.array_equal(o0[0][0], o3[0][0])
     assert np.array_equal(o0[0][0], o1[0][0])
 
 

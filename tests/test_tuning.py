@@ -34,3 +34,6 @@ def test_candidates_rules():
     assert any(v & 32 for _, v in big16) and any(not v & 32 for _, v in big16)
     odd16 = tune.candidates((16, 16, 33), "fp16")                # odd nx: one node per lane only
     assert all(v & 32 == 0 for _, v in odd16)
+    # the kernel without the tile loop (bit 128) only with one tile per block, and offered for it
+    assert all(not (v >> 2) & 3 for _, v in small if v & 128)
+    assert {v & ~128 for _, v in small if v & 128} == {v for _, v in small if not (v >> 2) & 3 and not v & 128}
