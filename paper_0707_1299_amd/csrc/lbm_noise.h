@@ -21,6 +21,16 @@ struct Philox4 {
     uint32_t v[4];
 };
 
+// Three-way XOR in one VALU instruction (v_bitop3_b32 with truth table 0x96: the
+// output bit is set where an odd number of the three input bits are).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Both callers pass a per-lane word 0 and wave-uniform words 1..3, so in the first
+// round the new word 0 is wave-uniform: it stays a plain XOR, which the compiler
+// keeps on the scalar unit; every other XOR of three words is one v_bitop3.
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                                  uint32_t k1)
 {
@@ -30,9 +40,9 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
         const uint64_t p0 = uint64_t(c0) * 0xD2511F53u, p1 = uint64_t(c2) * 0xCD9E8D57u;
         const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
         const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
-        c0 = hi1 ^ c1 ^ k0;
+        c0 = r == 0 ? hi1 ^ c1 ^ k0 : xor3(hi1, c1, k0);
         c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
+        c2 = xor3(hi0, c3, k1);
         c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
