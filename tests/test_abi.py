@@ -145,3 +145,20 @@ def test_copy_probe_rejects_bad_arguments_before_any_launch():
 def test_big_box_tiles_accepted(shape, storage, tile, variant):
     """Whole-wave tile rows are accepted for boxes over 4 GiB (and the default tile is one)."""
     assert lbm.lb_workspace_bytes(lbm.make_params(shape, storage, tile=tile, variant=variant)) > 0
+
+
+def test_tuned_entries_are_accepted_by_the_library():
+    """Every (tile, variant) in the shipped tuning cache passes the library's own parameter
+    checks for its storage and box shape (variant range, bit 128 only with one tile per block,
+    tile shapes, whole-wave rows for large boxes), so no tuned workload is refused at set-up."""
+    import json
+    from paper_0707_1299_amd import tune
+    cache = json.load(open(tune.CACHE))
+    assert cache
+    for key, e in cache.items():
+        _, storage, dims, boxes = key.split("/")[:4]
+        nx, ny, nz = map(int, dims.split("x"))
+        v = int(e["variant"])
+        assert 0 <= v <= 255 and not (v & 128 and (v >> 2) & 3), key
+        p = lbm.make_params((nz, ny, nx), storage, nboxes=int(boxes[1:]), tile=tuple(e["tile"]), variant=v)
+        assert lbm.lb_workspace_bytes(p) > 0, key
